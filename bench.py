@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Benchmark of the static bucketed cuckoo hash table on one MI355X.
+
+Workload (default): bucketed cuckoo table with three hash functions and
+16-slot (128-byte) buckets, 2^28 distinct uniform uint32 keys with random
+uint32 values at load factor 0.9, then 2^28 queries at each of 100%, 0% and
+50% positive.  One step = build + the three query batches; inputs are
+resident in HBM before timing starts.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--log2n 28] [--lf 0.9]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+WRITE_GRANULE = 64             # bytes charged per slot atomic (one HBM3E burst)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--lf", type=float, default=0.9)
+    ap.add_argument("--bucket", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=None)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-log2n", type=int, default=24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--out", default=None, help="also append the JSON line to this file")
+    return ap.parse_args()
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(probes):
+    """Bytes the method must move per key (Section VII-F cost model):
+    a probe reads one 128-byte bucket; every insertion step ends in one slot
+    atomic (a CAS or an exchange) charged one write granule; a query reads
+    its key and writes a 4-byte value and a 1-byte flag; a build reads an
+    8-byte pair."""
+    return {
+        "build": 8 + probes["insert"] * (128 + WRITE_GRANULE),
+        "find_pos": 9 + 128 * probes["pos"],
+        "find_neg": 9 + 128 * probes["neg"],
+        "find_mix": 9 + 128 * probes["mix"],
+    }
+
+
+def cpu_baseline(args, n_s):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import datagen
+    import oracle
+    keys, vals = datagen.unique_keys(n_s, args.seed), datagen.values(n_s, args.seed)
+    qs = {"find_pos": datagen.positive_queries(n_s, args.seed),
+          "find_neg": datagen.mixed_queries(n_s, n_s, 0.0, args.seed),
+          "find_mix": datagen.mixed_queries(n_s, n_s, 0.5, args.seed)}
+    params = None
+    for s in range(50):
+        params = oracle.params_for("bcht", n_s, args.lf, args.seed + 1000 * s, b=args.bucket)
+        t0 = time.perf_counter()
+        st, table, ins = oracle.build32(params, keys, vals)
+        t_build = time.perf_counter() - t0
+        if st == oracle.OK:
+            break
+    times = {"build": t_build}
+    probes = {"insert": ins / n_s}
+    for name, q in qs.items():
+        t0 = time.perf_counter()
+        _, _, pr, _ = oracle.find32(params, table, q)
+        times[name] = time.perf_counter() - t0
+        probes[name.replace("find_", "")] = pr / n_s
+    total = sum(times.values())
+    return {
+        "value": round(4 * n_s / total / 1e9, 6),
+        "unit": "Gkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "2^%d keys at LF %g (BCHT b=%d h=3), build + 2^%d queries at 100/0/50%% "
+                  "positive, serial C oracle, one thread" % (args.cpu_log2n, args.lf, args.bucket,
+                                                           args.cpu_log2n),
+        "seconds": {k: round(v, 3) for k, v in times.items()},
+        "rates_gkeys_s": {k: round(n_s / v / 1e9, 6) for k, v in times.items()},
+    }, probes
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2108_07232_amd as bht
+
+    n = 1 << args.log2n
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    log("generating inputs: 2^%d keys" % args.log2n)
+    t0 = time.time()
+    keys = datagen.unique_keys(n, args.seed)
+    vals = datagen.values(n, args.seed)
+    queries = {"find_pos": datagen.positive_queries(n, args.seed),
+               "find_neg": datagen.mixed_queries(n, n, 0.0, args.seed),
+               "find_mix": datagen.mixed_queries(n, n, 0.5, args.seed)}
+    d_keys = torch.from_numpy(keys.view(np.int32)).to(dev)
+    d_vals = torch.from_numpy(vals.view(np.int32)).to(dev)
+    d_q = {k: torch.from_numpy(v.view(np.int32)).to(dev) for k, v in queries.items()}
+    del keys, vals, queries
+    out_v = torch.empty(n, dtype=torch.int32, device=dev)
+    out_f = torch.empty(n, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    log("inputs resident in HBM (%.1f s)" % (time.time() - t0))
+
+    cap = datagen.capacity_for(n, args.lf)
+    seed_try = args.seed
+    a, c = datagen.hash_constants(seed_try, 3)
+    table = bht.Table(cap, args.bucket, "bcht", a, c, rng_seed=datagen.rng_seed(seed_try),
+                      tile=args.tile)
+    bht.bht_enable_timing(table.handle, True)
+    m, b, _, table_bytes = table.info
+    stream = torch.cuda.current_stream()
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    failures = 0
+
+    def step(record):
+        nonlocal failures, seed_try
+        e = {k: (ev(), ev()) for k in ("build", "find_pos", "find_neg", "find_mix")}
+        e["build"][0].record(stream)
+        bht.bht_build_async(table.handle, d_keys, d_vals, stream=stream)
+        e["build"][1].record(stream)
+        st = bht.bht_build_wait(table.handle, stream=stream)
+        while st == bht.BHT_ERR_BUILD_FAILED:
+            # Section VII: a failed build is retried with new hash constants
+            failures += 1
+            seed_try += 7919
+            a2, c2 = datagen.hash_constants(seed_try, 3)
+            bht.bht_reseed(table.handle, bht.make_params(a2, c2, rng_seed=datagen.rng_seed(seed_try)))
+            e["build"][0].record(stream)
+            bht.bht_build_async(table.handle, d_keys, d_vals, stream=stream)
+            e["build"][1].record(stream)
+            st = bht.bht_build_wait(table.handle, stream=stream)
+        if st != bht.BHT_OK:
+            raise RuntimeError("build failed: " + bht.bht_status_string(st))
+        build_kernel_ms, _ = bht.bht_kernel_ms(table.handle)
+        find_kernel_ms = {}
+        for name in ("find_pos", "find_neg", "find_mix"):
+            e[name][0].record(stream)
+            bht.bht_find(table.handle, d_q[name], out_v, out_f, stream=stream)
+            e[name][1].record(stream)
+        torch.cuda.synchronize()
+        for name in ("find_pos", "find_neg", "find_mix"):
+            find_kernel_ms[name] = e[name][0].elapsed_time(e[name][1])
+        if record is not None:
+            record["build_phase"].append(e["build"][0].elapsed_time(e["build"][1]))
+            record["build"].append(build_kernel_ms)
+            for name, ms in find_kernel_ms.items():
+                record[name].append(ms)
+
+    log("warmup %d steps" % args.warmup)
+    for _ in range(args.warmup):
+        step(None)
+    rec = {k: [] for k in ("build_phase", "build", "find_pos", "find_neg", "find_mix")}
+    log("timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(rec)
+        log("step %d done" % i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    # correctness spot check of the last step's mixed batch against the
+    # generator's membership (positives found, negatives absent)
+    found_mix = int(out_f.sum().item())
+
+    kernel_ms = {k: float(np.mean(v)) for k, v in rec.items()}
+    cpu = None
+    probes = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on 2^%d keys" % args.cpu_log2n)
+        cpu, probes = cpu_baseline(args, 1 << args.cpu_log2n)
+    bytes_per = algorithmic_bytes(probes) if probes else None
+
+    kernels = {}
+    for name in ("build", "find_pos", "find_neg", "find_mix"):
+        ms = kernel_ms[name]
+        entry = {"ms": round(ms, 4), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 4)}
+        if bytes_per:
+            gbs = bytes_per[name] * n / (ms * 1e-3) / 1e9
+            entry.update({"bytes_per_key": round(bytes_per[name], 2), "achieved_gbs": round(gbs, 1),
+                          "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
+        kernels[name] = entry
+    dominant = max(("build", "find_pos", "find_neg", "find_mix"), key=lambda k: kernel_ms[k])
+    roofline = None
+    if bytes_per:
+        ach = kernels[dominant]["achieved_gbs"]
+        roofline = {"bound": "hbm", "kernel": dominant, "achieved": ach, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+
+    total_ops = args.steps * 4 * n
+    result = {
+        "metric": "Gkeys/s build + Gqueries/s (pos/neg) at LF 0.9",
+        "value": round(total_ops / wall / 1e9, 4),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "BCHT h=3 b=%d, 2^%d uniform unique u32 keys + u32 values, LF %g; "
+                               "2^%d queries each at 100%%/0%%/50%% positive"
+                               % (args.bucket, args.log2n, args.lf, args.log2n),
+                   "n_keys": n, "load_factor": args.lf, "buckets": m, "bucket_slots": b,
+                   "table_bytes": table_bytes, "hashes": 3, "max_chain": 128},
+        "rates_gkeys_s": {"build": kernels["build"]["gkeys_s"],
+                          "build_with_reset": round(n / (kernel_ms["build_phase"] * 1e-3) / 1e9, 4),
+                          "find_pos": kernels["find_pos"]["gkeys_s"],
+                          "find_neg": kernels["find_neg"]["gkeys_s"],
+                          "find_mix": kernels["find_mix"]["gkeys_s"]},
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "probes_per_key_oracle": {k: round(v, 4) for k, v in probes.items()} if probes else None,
+        "build_failures": failures,
+        "mixed_found": found_mix,
+        "paper_context": {"hardware": "NVIDIA TITAN V", "build_gkeys_s": 1.34438,
+                          "find_pos_gq_s": 3.79958, "find_neg_gq_s": 2.35995,
+                          "find_mix_gq_s": 2.92174, "source": "Table III, BCHT b=16, LF 0.9"},
+    }
+    line = json.dumps(result)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "a") as f:
+            f.write(line + "\n")
+    table.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -5,6 +5,9 @@ arithmetic (no hashing into buckets, no probing, no placement), so both the
 CPU oracle and the GPU library can be fed from it without sharing any of the
 method's code.
 
+The bulk generators run in ``gen.c`` (plain C with OpenMP), loaded with
+ctypes; 2^28-key workloads take about a second.
+
 Workload shape (paper, Section VII): unique keys drawn uniformly from the
 32-bit unsigned range, random 32-bit values, positive queries that are the
 inserted keys in shuffled order and negative queries that are uniform keys
@@ -20,7 +23,10 @@ sides explicitly.
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
+import subprocess
 
 import numpy as np
 
@@ -63,116 +69,134 @@ def _seed(seed: int, tag: int) -> int:
     return (SEED_BASE ^ int(seed) ^ (tag << 56)) & 0xFFFFFFFFFFFFFFFF
 
 
-def _fmix32(x: np.ndarray) -> np.ndarray:
-    with np.errstate(over="ignore"):
-        x = x ^ (x >> np.uint32(16))
-        x = x * np.uint32(0x85EBCA6B)
-        x = x ^ (x >> np.uint32(13))
-        x = x * np.uint32(0xC2B2AE35)
-        x = x ^ (x >> np.uint32(16))
-    return x
+# ----------------------------------------------------- native generator
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gen.c")
+_LIB = os.path.join(_HERE, "libdatagen.so")
+_lib = None
 
 
-def feistel32(x: np.ndarray, round_keys) -> np.ndarray:
-    """Keyed bijection of [0, 2^32): four Feistel rounds over 16-bit halves."""
-    x = np.asarray(x, dtype=np.uint32)
-    left = x >> np.uint32(16)
-    right = x & np.uint32(0xFFFF)
-    for rk in round_keys:
-        with np.errstate(over="ignore"):
-            f = _fmix32(right * np.uint32(0x9E3779B1) + np.uint32(rk & 0xFFFFFFFF))
-        left, right = right, (left ^ (f >> np.uint32(16))) & np.uint32(0xFFFF)
-    return (left << np.uint32(16)) | right
+def build_library(force: bool = False) -> str:
+    """Compile gen.c with gcc (OpenMP) into libdatagen.so next to the source."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
 
 
-def _fmix64(x: np.ndarray) -> np.ndarray:
-    with np.errstate(over="ignore"):
-        x = x ^ (x >> np.uint64(33))
-        x = x * np.uint64(0xFF51AFD7ED558CCD)
-        x = x ^ (x >> np.uint64(33))
-        x = x * np.uint64(0xC4CEB9FE1A85EC53)
-        x = x ^ (x >> np.uint64(33))
-    return x
+def _native():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build_library())
+        u32, u64, p = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
+        _lib.dg_splitmix64.argtypes = [u64, u64, u64, p]
+        _lib.dg_values32.argtypes = [u64, u64, p]
+        _lib.dg_feistel32.restype = u32
+        _lib.dg_feistel32.argtypes = [u32, u32, u32, u32, u32]
+        _lib.dg_feistel64.restype = u64
+        _lib.dg_feistel64.argtypes = [u64, u64, u64, u64, u64]
+        _lib.dg_keys32.argtypes = [p, u64, u64, p]
+        _lib.dg_keys64.argtypes = [p, u64, u64, p]
+        _lib.dg_permutation.argtypes = [p, u64, p]
+        _lib.dg_queries32.argtypes = [p, p, u64, p, u64, u64, ctypes.c_int, p]
+        _lib.dg_queries64.argtypes = [p, p, u64, p, u64, u64, ctypes.c_int, p]
+    return _lib
 
 
-def feistel64(x: np.ndarray, round_keys) -> np.ndarray:
-    """Keyed bijection of [0, 2^64): four Feistel rounds over 32-bit halves."""
-    x = np.asarray(x, dtype=np.uint64)
-    left = x >> np.uint64(32)
-    right = x & np.uint64(0xFFFFFFFF)
-    for rk in round_keys:
-        with np.errstate(over="ignore"):
-            f = _fmix64(right * np.uint64(0x9E3779B97F4A7C15) + np.uint64(rk))
-        left, right = right, (left ^ (f >> np.uint64(32))) & np.uint64(0xFFFFFFFF)
-    return (left << np.uint64(32)) | right
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
 
 
-def _round_keys(seed: int, tag: int) -> list:
-    return [int(v) for v in splitmix64(_seed(seed, tag), 4)]
+def splitmix64_native(seed: int, count: int, start: int = 0) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint64)
+    if count:
+        _native().dg_splitmix64(seed & 0xFFFFFFFFFFFFFFFF, start, count, _ptr(out))
+    return out
 
 
-def _distinct32(idx: np.ndarray, seed: int) -> np.ndarray:
-    """Images of distinct indices under a bijection of [0,2^32) minus the sentinel.
+def _round_keys(seed: int, tag: int) -> np.ndarray:
+    return splitmix64(_seed(seed, tag), 4)
 
-    The sentinel is cycle-walked: the one index mapped onto it is sent to the
-    image of the sentinel itself, which no other index in range can reach.
-    """
-    rk = _round_keys(seed, TAG_KEYS)
-    y = feistel32(idx, rk)
-    hit = y == np.uint32(SENTINEL32)
-    if hit.any():
-        y[hit] = feistel32(np.array([SENTINEL32], dtype=np.uint32), rk)[0]
-    return y
+
+def feistel32(x: int, seed: int) -> int:
+    """The keyed 32-bit permutation used for keys (one value)."""
+    rk = [int(v) & 0xFFFFFFFF for v in _round_keys(seed, TAG_KEYS)]
+    return int(_native().dg_feistel32(x, *rk))
+
+
+def _keys32(start: int, count: int, seed: int) -> np.ndarray:
+    rk = (_round_keys(seed, TAG_KEYS) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    out = np.empty(count, dtype=np.uint32)
+    if count:
+        _native().dg_keys32(_ptr(rk), start, count, _ptr(out))
+    return out
 
 
 def unique_keys(n: int, seed: int) -> np.ndarray:
     """n distinct uniform uint32 keys, none equal to the sentinel."""
     if n >= SENTINEL32:
         raise ValueError("too many keys for the 32-bit key space")
-    return _distinct32(np.arange(n, dtype=np.uint32), seed)
+    return _keys32(0, n, seed)
 
 
 def negative_keys(count: int, n_inserted: int, seed: int) -> np.ndarray:
     """count uniform uint32 keys disjoint from unique_keys(n_inserted, seed)."""
     if n_inserted + count >= SENTINEL32:
         raise ValueError("key space exhausted")
-    idx = np.arange(n_inserted, n_inserted + count, dtype=np.uint64).astype(np.uint32)
-    return _distinct32(idx, seed)
+    return _keys32(n_inserted, count, seed)
 
 
 def values(n: int, seed: int) -> np.ndarray:
     """n uniform uint32 values (any value, the sentinel included)."""
-    return (splitmix64(_seed(seed, TAG_VALUES), n) >> np.uint64(32)).astype(np.uint32)
+    out = np.empty(n, dtype=np.uint32)
+    if n:
+        _native().dg_values32(_seed(seed, TAG_VALUES), n, _ptr(out))
+    return out
 
 
 def permutation(n: int, seed: int, tag: int = TAG_PERM) -> np.ndarray:
-    """A seeded uniform permutation of 0..n-1 (int64 indices)."""
-    return np.random.Generator(np.random.PCG64(_seed(seed, tag))).permutation(n)
+    """A seeded permutation of 0..n-1 (int64): a keyed Feistel bijection."""
+    out = np.empty(n, dtype=np.int64)
+    if n:
+        rk = _round_keys(seed, tag)
+        _native().dg_permutation(_ptr(rk), n, _ptr(out))
+    return out
 
 
-def positive_queries(keys: np.ndarray, seed: int) -> np.ndarray:
-    """The inserted keys in shuffled order."""
-    return keys[permutation(len(keys), seed)]
+def _queries(n: int, count: int, npos: int, seed: int, shuffle: bool, wide: bool):
+    rk_keys = _round_keys(seed, TAG_KEYS)
+    if not wide:
+        rk_keys = (rk_keys & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    rk_pos = _round_keys(seed, TAG_PERM)
+    rk_mix = _round_keys(seed, TAG_MIX)
+    out = np.empty(count, dtype=np.uint64 if wide else np.uint32)
+    if count:
+        fn = _native().dg_queries64 if wide else _native().dg_queries32
+        fn(_ptr(rk_keys), _ptr(rk_pos), n, _ptr(rk_mix), count, npos, int(shuffle), _ptr(out))
+    return out
 
 
-def mixed_queries(keys: np.ndarray, count: int, positive_fraction: float, seed: int):
-    """count queries, floor(fraction*count) of them inserted keys, the rest absent.
+def positive_queries(n: int, seed: int, wide: bool = False) -> np.ndarray:
+    """The n inserted keys of the seed's key stream, in shuffled order."""
+    return _queries(n, n, n, seed, False, wide)
 
-    Positives are a prefix of a shuffle of the inserted keys (repeating the
-    shuffle if count exceeds the key count); negatives come from the disjoint
-    key stream.  The union is shuffled again.  Returns the query array.
+
+def mixed_queries(n: int, count: int, positive_fraction: float, seed: int,
+                  wide: bool = False) -> np.ndarray:
+    """count queries against the first n keys of the seed's key stream.
+
+    floor(fraction * count) of them are inserted keys (a prefix of the
+    positive shuffle, repeated if it exceeds n); the rest are the keys that
+    follow the n inserted ones in the stream, hence absent.  The union is
+    shuffled.
     """
-    n = len(keys)
     npos = int(math.floor(positive_fraction * count))
     if npos > 0 and n == 0:
         raise ValueError("positive queries requested from an empty key set")
-    pos_idx = permutation(n, seed)[: min(npos, n)] if n else np.zeros(0, np.int64)
-    if npos > n:
-        pos_idx = np.resize(pos_idx, npos)
-    pos = keys[pos_idx]
-    neg = negative_keys(count - npos, n, seed)
-    q = np.concatenate([pos, neg])
-    return q[permutation(count, seed, TAG_MIX)]
+    return _queries(n, count, npos, seed, True, wide)
 
 
 def hash_constants(seed: int, h: int):
@@ -211,37 +235,25 @@ def rng_seed(seed: int) -> int:
     return s or 0x9E3779B9
 
 
+def _keys64(start: int, count: int, seed: int) -> np.ndarray:
+    rk = _round_keys(seed, TAG_KEYS)
+    out = np.empty(count, dtype=np.uint64)
+    if count:
+        _native().dg_keys64(_ptr(rk), start, count, _ptr(out))
+    return out
+
+
 def unique_keys64(n: int, seed: int) -> np.ndarray:
     """n distinct uniform uint64 keys, none equal to the all-ones sentinel."""
-    rk = _round_keys(seed, TAG_KEYS)
-    y = feistel64(np.arange(n, dtype=np.uint64), rk)
-    hit = y == np.uint64(SENTINEL64)
-    if hit.any():
-        y[hit] = feistel64(np.array([SENTINEL64], dtype=np.uint64), rk)[0]
-    return y
+    return _keys64(0, n, seed)
 
 
 def negative_keys64(count: int, n_inserted: int, seed: int) -> np.ndarray:
-    rk = _round_keys(seed, TAG_KEYS)
-    y = feistel64(np.arange(n_inserted, n_inserted + count, dtype=np.uint64), rk)
-    hit = y == np.uint64(SENTINEL64)
-    if hit.any():
-        y[hit] = feistel64(np.array([SENTINEL64], dtype=np.uint64), rk)[0]
-    return y
+    return _keys64(n_inserted, count, seed)
 
 
 def values64(n: int, seed: int) -> np.ndarray:
-    return splitmix64(_seed(seed, TAG_VALUES), n)
-
-
-def mixed_queries64(keys: np.ndarray, count: int, positive_fraction: float, seed: int):
-    n = len(keys)
-    npos = int(math.floor(positive_fraction * count))
-    pos_idx = permutation(n, seed)[: min(npos, n)] if n else np.zeros(0, np.int64)
-    if npos > n:
-        pos_idx = np.resize(pos_idx, npos)
-    q = np.concatenate([keys[pos_idx], negative_keys64(count - npos, n, seed)])
-    return q[permutation(count, seed, TAG_MIX)]
+    return splitmix64_native(_seed(seed, TAG_VALUES), n)
 
 
 def capacity_for(n: int, load_factor: float) -> int:

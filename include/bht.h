@@ -1,0 +1,187 @@
+/*
+ * bht — static bucketed hash tables on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library libbht.so.  Every entry point is extern "C", takes
+ * plain pointers and sizes, and returns a bht_status (no exceptions cross
+ * the boundary).  The operations are those of "Better GPU Hash Tables"
+ * (Awad, Ashkiani, Porumbescu, Farach-Colton, Owens; arXiv 2108.07232):
+ * a table is built once from an unordered list of key-value pairs and then
+ * answers positive and negative lookups (Section I; Section III).
+ *
+ * Schemes (Section III, Section VII):
+ *   BHT_BCHT   bucketed cuckoo table, h hash functions (3 by default), keys
+ *              cuckoo between buckets, queries stop early at a bucket with
+ *              room (Section III-A, Section V-B).
+ *   BHT_BP2HT  bucketed power-of-two-choices table: two hashes, a key goes to
+ *              the less loaded bucket and never moves (Section III-B, V-C).
+ *   BHT_IHT    iceberg table: primary bucket while it holds fewer than t
+ *              keys, else the less loaded of two secondary buckets (Section
+ *              III-C, V-D); optionally with a separate secondary level.
+ *   BHT_CHT1   cuckoo table with one slot per bucket (bucket_size = 1), the
+ *              classic GPU cuckoo layout the paper compares against.
+ *
+ * Device memory layout (library-owned, 256-byte aligned):
+ *   32-bit tables: one 8-byte slot per pair, key in the low 32 bits and value
+ *     in the high 32 bits; an empty slot is 0xFFFFFFFFFFFFFFFF.  Bucket i is
+ *     slots [i*b, (i+1)*b); with b = 16 a bucket is one 128-byte line.  An
+ *     iceberg table with a secondary level stores its m2*b2 secondary slots
+ *     right after the m*b primary slots.
+ *   64-bit tables: one 16-byte slot per pair (key word, then value word);
+ *     empty key word is 0xFFFFFFFFFFFFFFFF; b = 8 makes a 128-byte bucket.
+ *
+ * Hash family (Section VII): H_i(k) = ((a_i*k + b_i) mod p) mod m with
+ * p = 4294967291 for 32-bit keys; for 64-bit keys p = 2^61 - 1.  The caller
+ * supplies the constants (a_i in [1, p-1], b_i in [0, p-1]).
+ *
+ * Keys: unique within one build (duplicates are memory-safe but which value
+ * a lookup returns is then unspecified); the all-ones key is reserved as
+ * the empty marker and is rejected.  Values are unrestricted: a lookup
+ * reports presence separately from the value.
+ *
+ * Pointers named d_* are device pointers (hipMalloc or a framework's device
+ * allocation) owned by the caller; the library reads or writes them only
+ * during the call's stream work.  stream is a hipStream_t passed as void*
+ * (NULL = the null stream).  Calls on one table are not thread-safe with
+ * respect to each other, except concurrent finds on a built table.
+ */
+#ifndef BHT_H
+#define BHT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bht_table bht_table;
+
+typedef enum {
+  BHT_BCHT = 0,
+  BHT_BP2HT = 1,
+  BHT_IHT = 2,
+  BHT_CHT1 = 3
+} bht_scheme;
+
+typedef enum {
+  BHT_OK = 0,
+  BHT_ERR_INVALID_ARG = 1,   /* null pointer, bad size, bad parameters          */
+  BHT_ERR_CAPACITY = 2,      /* more pairs than slots                           */
+  BHT_ERR_SENTINEL_KEY = 3,  /* an input key equals the reserved empty key      */
+  BHT_ERR_BUILD_FAILED = 4,  /* eviction cap reached or every candidate full;   */
+                             /* table contents unspecified: reseed and rebuild  */
+  BHT_ERR_NOT_BUILT = 5,     /* find before a successful build                  */
+  BHT_ERR_OOM = 6,           /* device allocation failed                        */
+  BHT_ERR_HIP = 7,           /* a HIP runtime call failed (see bht_last_error)  */
+  BHT_ERR_UNSUPPORTED = 8    /* parameter combination not implemented           */
+} bht_status;
+
+typedef struct {
+  uint32_t num_hashes;        /* BCHT 1..4 (3 default), BP2HT 2, IHT 3, CHT1 1..4 */
+  uint32_t key_bits;          /* 32 or 64 (64: BCHT only)                         */
+  uint64_t a[4];              /* hash multipliers a_i                             */
+  uint64_t b[4];              /* hash offsets b_i                                 */
+  uint32_t rng_seed;          /* eviction victim generator seed (layout only)     */
+  uint32_t max_chain;         /* cuckoo: evictions allowed per insertion (128)    */
+  uint32_t iht_threshold;     /* IHT: primary used while its load is below this   */
+  uint32_t iht_secondary_b;   /* IHT: slots per secondary bucket, 0 = one level   */
+  uint64_t iht_secondary_m;   /* IHT: number of secondary buckets                 */
+} bht_params;
+
+/* Creates an empty table with m = ceil(capacity_slots / bucket_size)
+ * buckets (Section III: capacity C = m*b).  bucket_size: 1 (CHT1), or 8, 16
+ * or 32 (32-bit keys; BCHT also 4); 8 for 64-bit keys.  Allocates the slot
+ * array with hipMalloc on the current device.  *out receives the table. */
+bht_status bht_create(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme scheme,
+                      const bht_params* params, bht_table** out);
+
+/* Frees the table (NULL is accepted). */
+void bht_destroy(bht_table* t);
+
+/* Replaces the hash constants and generator seed (after BUILD_FAILED,
+ * Section VII: failed builds are retried with new constants).  The table
+ * must be built again. */
+bht_status bht_reseed(bht_table* t, const bht_params* params);
+
+/* Bulk build from n pairs (d_keys[i], d_values[i]), structure-of-arrays
+ * uint32.  Resets every slot to empty and inserts all pairs with the
+ * scheme's algorithm (Section III; Section V).  Waits for the stream to read
+ * the device status, so the return value reports BUILD_FAILED or
+ * SENTINEL_KEY.  n = 0 is valid; n above the slot count is CAPACITY. */
+bht_status bht_build(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,
+                     uint64_t n, void* stream);
+
+/* As bht_build but only enqueues the work; bht_build_wait then waits for
+ * the stream and returns the build's status.  Lets callers time or overlap
+ * the build. */
+bht_status bht_build_async(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,
+                           uint64_t n, void* stream);
+bht_status bht_build_wait(bht_table* t, void* stream);
+
+/* Bulk find of n queries (Section III; Section V).  d_out_values[i] is the
+ * value stored with d_queries[i], or 0xFFFFFFFF when absent; d_out_found[i]
+ * is 1 when present, else 0.  Asynchronous on stream; the table must be
+ * built.  Query 0xFFFFFFFF is always absent. */
+bht_status bht_find(const bht_table* t, const uint32_t* d_queries, uint64_t n,
+                    uint32_t* d_out_values, uint8_t* d_out_found, void* stream);
+
+/* 64-bit keys and values (bucketed cuckoo, 16-byte slots). */
+bht_status bht_build64(bht_table* t, const uint64_t* d_keys, const uint64_t* d_values,
+                       uint64_t n, void* stream);
+bht_status bht_find64(const bht_table* t, const uint64_t* d_queries, uint64_t n,
+                      uint64_t* d_out_values, uint8_t* d_out_found, void* stream);
+
+/* Instrumented variants counting probes, a probe being one bucket read
+ * (Section VII-E).  bht_build_counted adds the build's bucket reads to
+ * *d_probe_total (device uint64).  bht_find_counted writes each query's
+ * bucket reads to d_probes[i] (device uint8).  Not meant for timing. */
+bht_status bht_build_counted(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,
+                             uint64_t n, uint64_t* d_probe_total, void* stream);
+bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint64_t n,
+                            uint32_t* d_out_values, uint8_t* d_out_found, uint8_t* d_probes,
+                            void* stream);
+
+/* Tuning: lanes per tile that read one bucket together (1 for bucket_size
+ * 1; 4, 8 or 16 otherwise, at most bucket_size).  Changes speed only, never
+ * results. */
+bht_status bht_set_tile(bht_table* t, uint32_t tile_width);
+
+/* Profiling: when enabled, HIP events are recorded on the call's stream
+ * right before and after the main kernel of each build (the insertion
+ * kernel, not the table reset) and each find.  bht_kernel_ms waits for the
+ * events and returns the last build's and last find's kernel time in
+ * milliseconds (-1 when none was recorded). */
+bht_status bht_enable_timing(bht_table* t, int on);
+bht_status bht_kernel_ms(const bht_table* t, float* build_ms, float* find_ms);
+
+/* Geometry: number of (primary) buckets, slots per bucket, pairs stored by
+ * the last successful build, and total bytes of the slot array. */
+bht_status bht_info(const bht_table* t, uint64_t* num_buckets, uint32_t* bucket_size,
+                    uint64_t* n_stored, uint64_t* table_bytes);
+
+/* Copies the raw slot array (table_bytes from bht_info) to host memory, for
+ * layout checks.  Synchronous. */
+bht_status bht_download(const bht_table* t, void* host_slots);
+
+/* Replaces the slot array with a host layout (table_bytes bytes) holding
+ * n_stored pairs and marks the table built (tests: query a layout built
+ * elsewhere).  Synchronous. */
+bht_status bht_upload(bht_table* t, const void* host_slots, uint64_t n_stored);
+
+/* Device address of the slot array (for callers that query several tables
+ * in one launch). */
+bht_status bht_device_slots(const bht_table* t, void** d_slots);
+
+/* Host copy of the library's hash, for checking its arithmetic without a
+ * GPU: ((a*k + b) mod p) mod m with the 32-bit family, and with the 64-bit
+ * family. */
+uint64_t bht_hash32(uint64_t a, uint64_t b, uint32_t k, uint64_t m);
+uint64_t bht_hash64(uint64_t a, uint64_t b, uint64_t k, uint64_t m);
+
+/* Human-readable status name, and the calling thread's last error detail. */
+const char* bht_status_string(bht_status s);
+const char* bht_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -366,9 +366,31 @@ void orc_find64(const orc_params* p, const uint64_t* table, const uint64_t* q,
 
 /* ------------------------------------------------------------ brute force */
 
-static int cmp_u64(const void* x, const void* y) {
-  uint64_t a = *(const uint64_t*)x, b = *(const uint64_t*)y;
-  return (a > b) - (a < b);
+/* Ascending sort of n uint64 values: least-significant-digit radix sort,
+ * four passes over 16-bit digits (linear time keeps full-size checks short). */
+static void sort_u64(uint64_t* a, uint64_t n) {
+  if (n < 2) return;
+  uint64_t* tmp = (uint64_t*)malloc(n * sizeof(uint64_t));
+  uint64_t* count = (uint64_t*)malloc(65536 * sizeof(uint64_t));
+  uint64_t *src = a, *dst = tmp;
+  for (int pass = 0; pass < 4; pass++) {
+    int shift = 16 * pass;
+    memset(count, 0, 65536 * sizeof(uint64_t));
+    for (uint64_t i = 0; i < n; i++) count[(src[i] >> shift) & 0xFFFF]++;
+    uint64_t sum = 0;
+    for (int d = 0; d < 65536; d++) {
+      uint64_t c = count[d];
+      count[d] = sum;
+      sum += c;
+    }
+    for (uint64_t i = 0; i < n; i++) dst[count[(src[i] >> shift) & 0xFFFF]++] = src[i];
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+  }
+  /* four passes: the sorted data is back in a */
+  free(tmp);
+  free(count);
 }
 
 /* Section I: a lookup returns the value stored with the key, or reports the
@@ -377,7 +399,7 @@ void orc_brute_find32(const uint32_t* keys, const uint32_t* vals, uint64_t n,
                       const uint32_t* q, uint64_t nq, uint32_t* out_v, uint8_t* out_f) {
   uint64_t* s = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
   for (uint64_t i = 0; i < n; i++) s[i] = ((uint64_t)keys[i] << 32) | vals[i];
-  qsort(s, n, sizeof(uint64_t), cmp_u64);
+  sort_u64(s, n);
   for (uint64_t i = 0; i < nq; i++) {
     uint64_t lo = 0, hi = n;   /* first index with key >= q */
     while (lo < hi) {
@@ -494,8 +516,8 @@ int orc_check32(const orc_params* p, const uint64_t* t, const uint32_t* keys,
   for (uint64_t w = 0; w < words; w++)
     if (key_of(t[w]) != EMPTY32) a[j++] = ((uint64_t)key_of(t[w]) << 32) | val_of(t[w]);
   for (uint64_t i = 0; i < n; i++) b[i] = ((uint64_t)keys[i] << 32) | vals[i];
-  qsort(a, n, sizeof(uint64_t), cmp_u64);
-  qsort(b, n, sizeof(uint64_t), cmp_u64);
+  sort_u64(a, n);
+  sort_u64(b, n);
   for (uint64_t i = 0; i < n; i++) {
     if (a[i] != b[i]) {
       snprintf(msg, msglen, "I1: stored pair (%u,%u) differs from input pair (%u,%u)",

@@ -1,0 +1,324 @@
+"""Static bucketed hash tables for AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding of ``libbht.so`` (C ABI in ``include/bht.h``): argument
+marshalling only.  Building and querying run in the library's HIP kernels;
+PyTorch supplies device memory and streams.  If the library has not been
+built, importing this package raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbht.so")
+
+BHT_BCHT, BHT_BP2HT, BHT_IHT, BHT_CHT1 = 0, 1, 2, 3
+SCHEMES = {"bcht": BHT_BCHT, "bp2ht": BHT_BP2HT, "iht": BHT_IHT, "cht1": BHT_CHT1}
+
+STATUS = {
+    0: "BHT_OK", 1: "BHT_ERR_INVALID_ARG", 2: "BHT_ERR_CAPACITY", 3: "BHT_ERR_SENTINEL_KEY",
+    4: "BHT_ERR_BUILD_FAILED", 5: "BHT_ERR_NOT_BUILT", 6: "BHT_ERR_OOM", 7: "BHT_ERR_HIP",
+    8: "BHT_ERR_UNSUPPORTED",
+}
+BHT_OK, BHT_ERR_INVALID_ARG, BHT_ERR_CAPACITY, BHT_ERR_SENTINEL_KEY = 0, 1, 2, 3
+BHT_ERR_BUILD_FAILED, BHT_ERR_NOT_BUILT, BHT_ERR_OOM, BHT_ERR_HIP, BHT_ERR_UNSUPPORTED = 4, 5, 6, 7, 8
+
+
+class BhtError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__("%s: %s (%s)" % (where, STATUS.get(status, status), detail))
+        self.status = status
+
+
+class bht_params(ctypes.Structure):
+    _fields_ = [
+        ("num_hashes", ctypes.c_uint32),
+        ("key_bits", ctypes.c_uint32),
+        ("a", ctypes.c_uint64 * 4),
+        ("b", ctypes.c_uint64 * 4),
+        ("rng_seed", ctypes.c_uint32),
+        ("max_chain", ctypes.c_uint32),
+        ("iht_threshold", ctypes.c_uint32),
+        ("iht_secondary_b", ctypes.c_uint32),
+        ("iht_secondary_m", ctypes.c_uint64),
+    ]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libbht.so is not built; run __graft_entry__.build() "
+                      "(or python paper_2108_07232_amd/build.py) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_u32, _u64, _p, _st = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
+_pp = ctypes.POINTER(ctypes.c_void_p)
+
+_SIGS = {
+    "bht_create": (_st, [_u64, _u32, ctypes.c_int, ctypes.POINTER(bht_params), _pp]),
+    "bht_destroy": (None, [_p]),
+    "bht_reseed": (_st, [_p, ctypes.POINTER(bht_params)]),
+    "bht_build": (_st, [_p, _p, _p, _u64, _p]),
+    "bht_build_async": (_st, [_p, _p, _p, _u64, _p]),
+    "bht_build_wait": (_st, [_p, _p]),
+    "bht_find": (_st, [_p, _p, _u64, _p, _p, _p]),
+    "bht_build64": (_st, [_p, _p, _p, _u64, _p]),
+    "bht_find64": (_st, [_p, _p, _u64, _p, _p, _p]),
+    "bht_build_counted": (_st, [_p, _p, _p, _u64, _p, _p]),
+    "bht_find_counted": (_st, [_p, _p, _u64, _p, _p, _p, _p]),
+    "bht_set_tile": (_st, [_p, _u32]),
+    "bht_enable_timing": (_st, [_p, ctypes.c_int]),
+    "bht_kernel_ms": (_st, [_p, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "bht_info": (_st, [_p, ctypes.POINTER(_u64), ctypes.POINTER(_u32), ctypes.POINTER(_u64),
+                       ctypes.POINTER(_u64)]),
+    "bht_download": (_st, [_p, _p]),
+    "bht_upload": (_st, [_p, _p, _u64]),
+    "bht_device_slots": (_st, [_p, _pp]),
+    "bht_hash32": (_u64, [_u64, _u64, _u32, _u64]),
+    "bht_hash64": (_u64, [_u64, _u64, _u64, _u64]),
+    "bht_status_string": (ctypes.c_char_p, [_st]),
+    "bht_last_error": (ctypes.c_char_p, []),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = sorted(_SIGS)
+
+
+def _check(status: int, where: str):
+    if status != BHT_OK:
+        raise BhtError(status, where, (_lib.bht_last_error() or b"").decode())
+
+
+def _dptr(t, dtype=None, name="tensor"):
+    """Device address of a contiguous tensor (marshalling only)."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        if not t.is_cuda:
+            raise ValueError("%s must be a device tensor" % name)
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if dtype is not None and t.dtype != dtype:
+            raise ValueError("%s must have dtype %s, not %s" % (name, dtype, t.dtype))
+        return ctypes.c_void_p(t.data_ptr())
+    return ctypes.c_void_p(int(t))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def make_params(a, b, num_hashes=None, key_bits=32, rng_seed=0x9E3779B9, max_chain=128,
+                iht_threshold=0, iht_secondary_b=0, iht_secondary_m=0) -> bht_params:
+    p = bht_params()
+    p.num_hashes = len(a) if num_hashes is None else num_hashes
+    p.key_bits = key_bits
+    for i in range(4):
+        p.a[i] = int(a[i]) if i < len(a) else 0
+        p.b[i] = int(b[i]) if i < len(b) else 0
+    p.rng_seed = rng_seed & 0xFFFFFFFF
+    p.max_chain = max_chain
+    p.iht_threshold = iht_threshold
+    p.iht_secondary_b = iht_secondary_b
+    p.iht_secondary_m = iht_secondary_m
+    return p
+
+
+# ---------------------------------------------------- C ABI, same names
+
+def bht_create(capacity_slots: int, bucket_size: int, scheme, params: bht_params):
+    if isinstance(scheme, str):
+        scheme = SCHEMES[scheme]
+    out = ctypes.c_void_p()
+    _check(_lib.bht_create(capacity_slots, bucket_size, scheme, ctypes.byref(params),
+                           ctypes.byref(out)), "bht_create")
+    return out
+
+
+def bht_destroy(table):
+    _lib.bht_destroy(table)
+
+
+def bht_reseed(table, params: bht_params):
+    _check(_lib.bht_reseed(table, ctypes.byref(params)), "bht_reseed")
+
+
+def bht_build(table, keys, values, n=None, stream=None) -> int:
+    """Returns the status (BUILD_FAILED and SENTINEL_KEY are returned, not raised)."""
+    n = keys.numel() if n is None else n
+    st = _lib.bht_build(table, _dptr(keys, None, "keys"), _dptr(values, None, "values"), n,
+                        _stream(stream))
+    if st not in (BHT_OK, BHT_ERR_BUILD_FAILED, BHT_ERR_SENTINEL_KEY):
+        _check(st, "bht_build")
+    return st
+
+
+def bht_build_async(table, keys, values, n=None, stream=None):
+    n = keys.numel() if n is None else n
+    _check(_lib.bht_build_async(table, _dptr(keys, None, "keys"), _dptr(values, None, "values"),
+                                n, _stream(stream)), "bht_build_async")
+
+
+def bht_build_wait(table, stream=None) -> int:
+    st = _lib.bht_build_wait(table, _stream(stream))
+    if st not in (BHT_OK, BHT_ERR_BUILD_FAILED, BHT_ERR_SENTINEL_KEY):
+        _check(st, "bht_build_wait")
+    return st
+
+
+def bht_find(table, queries, out_values, out_found, n=None, stream=None):
+    n = queries.numel() if n is None else n
+    _check(_lib.bht_find(table, _dptr(queries, None, "queries"), n,
+                         _dptr(out_values, None, "out_values"),
+                         _dptr(out_found, None, "out_found"), _stream(stream)), "bht_find")
+
+
+def bht_build64(table, keys, values, n=None, stream=None) -> int:
+    n = keys.numel() if n is None else n
+    st = _lib.bht_build64(table, _dptr(keys, None, "keys"), _dptr(values, None, "values"), n,
+                          _stream(stream))
+    if st not in (BHT_OK, BHT_ERR_BUILD_FAILED, BHT_ERR_SENTINEL_KEY):
+        _check(st, "bht_build64")
+    return st
+
+
+def bht_find64(table, queries, out_values, out_found, n=None, stream=None):
+    n = queries.numel() if n is None else n
+    _check(_lib.bht_find64(table, _dptr(queries, None, "queries"), n,
+                           _dptr(out_values, None, "out_values"),
+                           _dptr(out_found, None, "out_found"), _stream(stream)), "bht_find64")
+
+
+def bht_build_counted(table, keys, values, probe_total, n=None, stream=None) -> int:
+    n = keys.numel() if n is None else n
+    st = _lib.bht_build_counted(table, _dptr(keys, None, "keys"), _dptr(values, None, "values"),
+                                n, _dptr(probe_total, None, "probe_total"), _stream(stream))
+    if st not in (BHT_OK, BHT_ERR_BUILD_FAILED, BHT_ERR_SENTINEL_KEY):
+        _check(st, "bht_build_counted")
+    return st
+
+
+def bht_find_counted(table, queries, out_values, out_found, probes, n=None, stream=None):
+    n = queries.numel() if n is None else n
+    _check(_lib.bht_find_counted(table, _dptr(queries, None, "queries"), n,
+                                 _dptr(out_values, None, "out_values"),
+                                 _dptr(out_found, None, "out_found"),
+                                 _dptr(probes, None, "probes"), _stream(stream)),
+           "bht_find_counted")
+
+
+def bht_set_tile(table, tile_width: int):
+    _check(_lib.bht_set_tile(table, tile_width), "bht_set_tile")
+
+
+def bht_enable_timing(table, on: bool = True):
+    _check(_lib.bht_enable_timing(table, int(on)), "bht_enable_timing")
+
+
+def bht_kernel_ms(table):
+    b, f = ctypes.c_float(), ctypes.c_float()
+    _check(_lib.bht_kernel_ms(table, ctypes.byref(b), ctypes.byref(f)), "bht_kernel_ms")
+    return b.value, f.value
+
+
+def bht_info(table):
+    m, b, n, nbytes = _u64(), _u32(), _u64(), _u64()
+    _check(_lib.bht_info(table, ctypes.byref(m), ctypes.byref(b), ctypes.byref(n),
+                         ctypes.byref(nbytes)), "bht_info")
+    return m.value, b.value, n.value, nbytes.value
+
+
+def bht_download(table):
+    import numpy as np
+    _, _, _, nbytes = bht_info(table)
+    out = np.empty(nbytes // 8, dtype=np.uint64)
+    _check(_lib.bht_download(table, ctypes.c_void_p(out.ctypes.data)), "bht_download")
+    return out
+
+
+def bht_upload(table, host_words, n_stored: int):
+    import numpy as np
+    host_words = np.ascontiguousarray(host_words, dtype=np.uint64)
+    _check(_lib.bht_upload(table, ctypes.c_void_p(host_words.ctypes.data), n_stored), "bht_upload")
+
+
+def bht_device_slots(table) -> int:
+    out = ctypes.c_void_p()
+    _check(_lib.bht_device_slots(table, ctypes.byref(out)), "bht_device_slots")
+    return out.value
+
+
+def bht_hash32(a: int, b: int, k: int, m: int) -> int:
+    return int(_lib.bht_hash32(a, b, k, m))
+
+
+def bht_hash64(a: int, b: int, k: int, m: int) -> int:
+    return int(_lib.bht_hash64(a, b, k, m))
+
+
+def bht_status_string(status: int) -> str:
+    return _lib.bht_status_string(status).decode()
+
+
+# ------------------------------------------------------- convenience
+
+class Table:
+    """One device table: owns the C handle, takes and returns torch tensors."""
+
+    def __init__(self, capacity_slots: int, bucket_size: int, scheme="bcht", a=(), b=(),
+                 key_bits=32, rng_seed=0x9E3779B9, max_chain=128, iht_threshold=0,
+                 iht_secondary_b=0, iht_secondary_m=0, tile=None):
+        self.params = make_params(a, b, key_bits=key_bits, rng_seed=rng_seed,
+                                  max_chain=max_chain, iht_threshold=iht_threshold,
+                                  iht_secondary_b=iht_secondary_b,
+                                  iht_secondary_m=iht_secondary_m)
+        self.key_bits = key_bits
+        self.handle = bht_create(capacity_slots, bucket_size, scheme, self.params)
+        if tile is not None:
+            bht_set_tile(self.handle, tile)
+
+    def close(self):
+        if self.handle:
+            bht_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self):
+        return bht_info(self.handle)
+
+    def build(self, keys, values, stream=None) -> int:
+        if self.key_bits == 64:
+            return bht_build64(self.handle, keys, values, stream=stream)
+        return bht_build(self.handle, keys, values, stream=stream)
+
+    def find(self, queries, stream=None):
+        import torch
+        if self.key_bits == 64:
+            out_v = torch.empty(queries.numel(), dtype=torch.int64, device=queries.device)
+            out_f = torch.empty(queries.numel(), dtype=torch.uint8, device=queries.device)
+            bht_find64(self.handle, queries, out_v, out_f, stream=stream)
+        else:
+            out_v = torch.empty(queries.numel(), dtype=torch.int32, device=queries.device)
+            out_f = torch.empty(queries.numel(), dtype=torch.uint8, device=queries.device)
+            bht_find(self.handle, queries, out_v, out_f, stream=stream)
+        return out_v, out_f
+
+    def download(self):
+        return bht_download(self.handle)
+
+    def upload(self, host_words, n_stored):
+        bht_upload(self.handle, host_words, n_stored)

@@ -1,0 +1,462 @@
+// C ABI of libbht: table objects, argument checking, launch geometry and
+// dispatch to the gfx950 kernels.  Declared in include/bht.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "bht.h"
+#include "bht_kernels.hpp"
+
+using namespace bht;
+
+struct bht_table {
+  bht_scheme scheme;
+  uint32_t b;           // slots per (primary) bucket
+  uint64_t m;           // (primary) buckets
+  uint32_t key_bits;
+  bht_params params;
+  uint32_t tile;        // lanes per tile reading one bucket
+  uint64_t* d_slots;
+  uint64_t words;       // uint64 words in the slot array
+  uint32_t* d_status;   // [0] flags
+  uint32_t* h_status;   // pinned host copy
+  uint64_t n_stored;
+  uint64_t pending_n;
+  bool built;
+  bool pending;
+  int device;
+  bool timing;             // record events around the main kernels
+  hipEvent_t ev[4];        // build start/stop, find start/stop
+  bool build_timed, find_timed;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bht_status fail(bht_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+bht_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return BHT_ERR_HIP;
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);   \
+  } while (0)
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Blocks to launch: enough to give every lane an item, capped at what the
+// device keeps resident at once (the kernels loop over their share).
+int grid_for(const void* kernel, uint64_t items) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> resident;
+  int cap;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = resident.find(kernel);
+    if (it == resident.end()) {
+      int dev = 0, cus = 0, per_cu = 0;
+      (void)hipGetDevice(&dev);
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0);
+      cap = std::max(1, cus) * std::max(1, per_cu);
+      resident.emplace(kernel, cap);
+    } else {
+      cap = it->second;
+    }
+  }
+  uint64_t want = (items + kBlock - 1) / kBlock;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)cap));
+}
+
+Hash32 make_hash32(const bht_params& p, uint64_t m, uint32_t h) {
+  Hash32 H;
+  for (int i = 0; i < 4; ++i) {
+    H.a[i] = (uint32_t)p.a[i];
+    H.c[i] = (uint32_t)p.b[i];
+  }
+  H.m = (uint32_t)m;
+  H.M = fastmod32_constant((uint32_t)m);
+  H.h = h;
+  return H;
+}
+
+bool valid_params(const bht_params& p, bht_scheme scheme, uint32_t b, std::string* why) {
+  if (p.key_bits != 32 && p.key_bits != 64) return *why = "key_bits must be 32 or 64", false;
+  const uint64_t prime = p.key_bits == 32 ? kP32 : kP61;
+  if (p.num_hashes < 1 || p.num_hashes > 4) return *why = "num_hashes must be 1..4", false;
+  for (uint32_t i = 0; i < p.num_hashes; ++i) {
+    if (p.a[i] < 1 || p.a[i] >= prime || p.b[i] >= prime)
+      return *why = "hash constants must satisfy 1 <= a < p and 0 <= b < p", false;
+  }
+  switch (scheme) {
+    case BHT_BCHT:
+      if (p.key_bits == 64 ? b != 8 : (b != 4 && b != 8 && b != 16 && b != 32))
+        return *why = "BCHT bucket size must be 4, 8, 16 or 32 (8 for 64-bit keys)", false;
+      break;
+    case BHT_CHT1:
+      if (b != 1 || p.key_bits != 32) return *why = "CHT1 needs bucket_size 1, 32-bit keys", false;
+      break;
+    default:
+      return *why = "scheme not available in this build", false;
+  }
+  return true;
+}
+
+uint32_t default_tile(uint32_t b) {
+  switch (b) {
+    case 1: return 1;
+    case 4: return 4;
+    case 8: return 8;
+    case 16: return 8;
+    default: return 16;
+  }
+}
+
+// --------------------------------------------------------------- dispatch
+
+using BuildKernel = void (*)(BuildArgs32);
+using FindKernel = void (*)(FindArgs32);
+
+template <int B, int W>
+struct Kern {
+  static constexpr BuildKernel build(bool count) {
+    return count ? cuckoo_build_kernel<B, W, true> : cuckoo_build_kernel<B, W, false>;
+  }
+  static constexpr FindKernel find(bool count) {
+    return count ? cuckoo_find_kernel<B, W, true> : cuckoo_find_kernel<B, W, false>;
+  }
+};
+
+bool pick_cuckoo(uint32_t b, uint32_t w, bool count, BuildKernel* bk, FindKernel* fk) {
+#define BHT_CASE(B_, W_)                       \
+  if (b == B_ && w == W_) {                    \
+    *bk = Kern<B_, W_>::build(count);          \
+    *fk = Kern<B_, W_>::find(count);           \
+    return true;                               \
+  }
+  BHT_CASE(1, 1)
+  BHT_CASE(4, 4)
+  BHT_CASE(8, 4)
+  BHT_CASE(8, 8)
+  BHT_CASE(16, 4)
+  BHT_CASE(16, 8)
+  BHT_CASE(16, 16)
+  BHT_CASE(32, 8)
+  BHT_CASE(32, 16)
+#undef BHT_CASE
+  return false;
+}
+
+bht_status launch_fill(bht_table* t, hipStream_t st) {
+  const uint64_t pairs = t->words / 2 + 1;
+  const int grid = (int)std::min<uint64_t>((pairs + kBlock - 1) / kBlock, 8192);
+  fill_empty_kernel<<<grid, kBlock, 0, st>>>(t->d_slots, t->words, t->d_status);
+  HIP_TRY(hipGetLastError());
+  return BHT_OK;
+}
+
+bht_status build32_enqueue(bht_table* t, const uint32_t* keys, const uint32_t* vals, uint64_t n,
+                           unsigned long long* probe_total, void* stream) {
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  if (t->key_bits != 32) return fail(BHT_ERR_INVALID_ARG, "table holds 64-bit keys");
+  if (n > t->m * (uint64_t)t->b) return fail(BHT_ERR_CAPACITY, "more pairs than slots");
+  if (n && (!keys || !vals)) return fail(BHT_ERR_INVALID_ARG, "null key or value pointer");
+  BuildKernel bk;
+  FindKernel fk;
+  if (!pick_cuckoo(t->b, t->tile, probe_total != nullptr, &bk, &fk))
+    return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
+  hipStream_t st = as_stream(stream);
+  t->built = false;
+  bht_status s = launch_fill(t, st);
+  if (s != BHT_OK) return s;
+  if (n) {
+    BuildArgs32 g;
+    g.slots = t->d_slots;
+    g.keys = keys;
+    g.vals = vals;
+    g.n = n;
+    g.status = t->d_status;
+    g.probe_total = probe_total;
+    g.H = make_hash32(t->params, t->m, t->params.num_hashes);
+    g.max_chain = t->params.max_chain;
+    g.rng_seed = t->params.rng_seed;
+    const int grid = grid_for((const void*)bk, n);
+    if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
+    bk<<<grid, kBlock, 0, st>>>(g);
+    HIP_TRY(hipGetLastError());
+    if (t->timing) HIP_TRY(hipEventRecord(t->ev[1], st));
+    t->build_timed = t->timing;
+  }
+  t->pending = true;
+  t->pending_n = n;
+  return BHT_OK;
+}
+
+bht_status find32_enqueue(const bht_table* t, const uint32_t* q, uint64_t n, uint32_t* out_v,
+                          uint8_t* out_f, uint8_t* probes, void* stream) {
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  if (t->key_bits != 32) return fail(BHT_ERR_INVALID_ARG, "table holds 64-bit keys");
+  if (!t->built) return fail(BHT_ERR_NOT_BUILT, "find before a successful build");
+  if (n == 0) return BHT_OK;
+  if (!q || !out_v || !out_f) return fail(BHT_ERR_INVALID_ARG, "null query or output pointer");
+  BuildKernel bk;
+  FindKernel fk;
+  if (!pick_cuckoo(t->b, t->tile, probes != nullptr, &bk, &fk))
+    return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
+  FindArgs32 g;
+  g.slots = t->d_slots;
+  g.queries = q;
+  g.n = n;
+  g.out_v = out_v;
+  g.out_f = out_f;
+  g.probes = probes;
+  g.H = make_hash32(t->params, t->m, t->params.num_hashes);
+  const int grid = grid_for((const void*)fk, n);
+  bht_table* mt = const_cast<bht_table*>(t);
+  if (t->timing) HIP_TRY(hipEventRecord(t->ev[2], as_stream(stream)));
+  fk<<<grid, kBlock, 0, as_stream(stream)>>>(g);
+  HIP_TRY(hipGetLastError());
+  if (t->timing) HIP_TRY(hipEventRecord(t->ev[3], as_stream(stream)));
+  mt->find_timed = t->timing;
+  return BHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bht_status_string(bht_status s) {
+  switch (s) {
+    case BHT_OK: return "ok";
+    case BHT_ERR_INVALID_ARG: return "invalid argument";
+    case BHT_ERR_CAPACITY: return "more pairs than slots";
+    case BHT_ERR_SENTINEL_KEY: return "input key equals the reserved empty key";
+    case BHT_ERR_BUILD_FAILED: return "build failed (reseed and rebuild)";
+    case BHT_ERR_NOT_BUILT: return "table not built";
+    case BHT_ERR_OOM: return "device allocation failed";
+    case BHT_ERR_HIP: return "HIP runtime error";
+    case BHT_ERR_UNSUPPORTED: return "unsupported parameters";
+  }
+  return "unknown status";
+}
+
+const char* bht_last_error(void) { return g_last_error.c_str(); }
+
+uint64_t bht_hash32(uint64_t a, uint64_t b, uint32_t k, uint64_t m) {
+  if (m == 0 || m > 0xFFFFFFFFull) return ~0ull;
+  return hash32((uint32_t)a, (uint32_t)b, k, fastmod32_constant((uint32_t)m), (uint32_t)m);
+}
+
+uint64_t bht_hash64(uint64_t a, uint64_t b, uint64_t k, uint64_t m) {
+  if (m == 0) return ~0ull;
+  return hash64(a, b, k, UINT64_MAX / m, m);
+}
+
+bht_status bht_create(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme scheme,
+                      const bht_params* params, bht_table** out) {
+  if (!out || !params) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (bucket_size == 0 || capacity_slots == 0) return fail(BHT_ERR_INVALID_ARG, "zero size");
+  std::string why;
+  if (!valid_params(*params, scheme, bucket_size, &why)) {
+    bool unsupported = why.find("not available") != std::string::npos;
+    return fail(unsupported ? BHT_ERR_UNSUPPORTED : BHT_ERR_INVALID_ARG, why);
+  }
+  const uint64_t m = (capacity_slots + bucket_size - 1) / bucket_size;
+  if (params->key_bits == 32 && m > 0xFFFFFFFFull)
+    return fail(BHT_ERR_INVALID_ARG, "more than 2^32 - 1 buckets");
+  bht_table* t = new bht_table();
+  t->scheme = scheme;
+  t->b = bucket_size;
+  t->m = m;
+  t->key_bits = params->key_bits;
+  t->params = *params;
+  if (t->params.max_chain == 0 && scheme != BHT_BCHT && scheme != BHT_CHT1) t->params.max_chain = 0;
+  t->tile = default_tile(bucket_size);
+  const uint64_t slot_words = params->key_bits == 64 ? 2 : 1;
+  t->words = m * bucket_size * slot_words;
+  hipError_t e = hipGetDevice(&t->device);
+  if (e == hipSuccess) e = hipMalloc(&t->d_slots, t->words * sizeof(uint64_t));
+  if (e != hipSuccess) {
+    delete t;
+    return fail(BHT_ERR_OOM, std::string("slot array: ") + hipGetErrorString(e));
+  }
+  e = hipMalloc(&t->d_status, 16);
+  if (e == hipSuccess) e = hipHostMalloc(&t->h_status, 16, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipFree(t->d_slots);
+    if (t->d_status) (void)hipFree(t->d_status);
+    delete t;
+    return fail(BHT_ERR_OOM, std::string("status word: ") + hipGetErrorString(e));
+  }
+  *out = t;
+  return BHT_OK;
+}
+
+void bht_destroy(bht_table* t) {
+  if (!t) return;
+  if (t->timing)
+    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(t->ev[i]);
+  (void)hipFree(t->d_slots);
+  (void)hipFree(t->d_status);
+  (void)hipHostFree(t->h_status);
+  delete t;
+}
+
+bht_status bht_reseed(bht_table* t, const bht_params* params) {
+  if (!t || !params) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  std::string why;
+  if (params->key_bits != t->key_bits || !valid_params(*params, t->scheme, t->b, &why))
+    return fail(BHT_ERR_INVALID_ARG, why.empty() ? "key width differs" : why);
+  t->params = *params;
+  t->built = false;
+  return BHT_OK;
+}
+
+bht_status bht_build_async(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,
+                           uint64_t n, void* stream) {
+  return build32_enqueue(t, d_keys, d_values, n, nullptr, stream);
+}
+
+bht_status bht_build_wait(bht_table* t, void* stream) {
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  if (!t->pending) return t->built ? BHT_OK : fail(BHT_ERR_NOT_BUILT, "no build pending");
+  hipStream_t st = as_stream(stream);
+  HIP_TRY(hipMemcpyAsync(t->h_status, t->d_status, 16, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  t->pending = false;
+  const uint32_t flags = t->h_status[0];
+  if (flags & kFlagSentinel) return fail(BHT_ERR_SENTINEL_KEY, "input holds key 0xFFFFFFFF");
+  if (flags & kFlagFailed) return fail(BHT_ERR_BUILD_FAILED, "eviction cap reached");
+  t->built = true;
+  t->n_stored = t->pending_n;
+  return BHT_OK;
+}
+
+bht_status bht_build(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n,
+                     void* stream) {
+  bht_status s = build32_enqueue(t, d_keys, d_values, n, nullptr, stream);
+  if (s != BHT_OK) return s;
+  return bht_build_wait(t, stream);
+}
+
+bht_status bht_build_counted(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,
+                             uint64_t n, uint64_t* d_probe_total, void* stream) {
+  if (!d_probe_total) return fail(BHT_ERR_INVALID_ARG, "null probe counter");
+  bht_status s = build32_enqueue(t, d_keys, d_values, n,
+                                 reinterpret_cast<unsigned long long*>(d_probe_total), stream);
+  if (s != BHT_OK) return s;
+  return bht_build_wait(t, stream);
+}
+
+bht_status bht_find(const bht_table* t, const uint32_t* d_queries, uint64_t n,
+                    uint32_t* d_out_values, uint8_t* d_out_found, void* stream) {
+  return find32_enqueue(t, d_queries, n, d_out_values, d_out_found, nullptr, stream);
+}
+
+bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint64_t n,
+                            uint32_t* d_out_values, uint8_t* d_out_found, uint8_t* d_probes,
+                            void* stream) {
+  if (!d_probes) return fail(BHT_ERR_INVALID_ARG, "null probe array");
+  return find32_enqueue(t, d_queries, n, d_out_values, d_out_found, d_probes, stream);
+}
+
+bht_status bht_build64(bht_table* t, const uint64_t* d_keys, const uint64_t* d_values,
+                       uint64_t n, void* stream) {
+  (void)t; (void)d_keys; (void)d_values; (void)n; (void)stream;
+  return fail(BHT_ERR_UNSUPPORTED, "64-bit keys not available in this build");
+}
+
+bht_status bht_find64(const bht_table* t, const uint64_t* d_queries, uint64_t n,
+                      uint64_t* d_out_values, uint8_t* d_out_found, void* stream) {
+  (void)t; (void)d_queries; (void)n; (void)d_out_values; (void)d_out_found; (void)stream;
+  return fail(BHT_ERR_UNSUPPORTED, "64-bit keys not available in this build");
+}
+
+bht_status bht_set_tile(bht_table* t, uint32_t tile_width) {
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  BuildKernel bk;
+  FindKernel fk;
+  if (!pick_cuckoo(t->b, tile_width, false, &bk, &fk))
+    return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
+  t->tile = tile_width;
+  return BHT_OK;
+}
+
+bht_status bht_enable_timing(bht_table* t, int on) {
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  if (on && !t->timing) {
+    for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&t->ev[i]));
+    t->timing = true;
+  }
+  return BHT_OK;
+}
+
+bht_status bht_kernel_ms(const bht_table* t, float* build_ms, float* find_ms) {
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  if (!t->timing) return fail(BHT_ERR_INVALID_ARG, "timing not enabled");
+  if (build_ms) {
+    *build_ms = -1.0f;
+    if (t->build_timed) {
+      HIP_TRY(hipEventSynchronize(t->ev[1]));
+      HIP_TRY(hipEventElapsedTime(build_ms, t->ev[0], t->ev[1]));
+    }
+  }
+  if (find_ms) {
+    *find_ms = -1.0f;
+    if (t->find_timed) {
+      HIP_TRY(hipEventSynchronize(t->ev[3]));
+      HIP_TRY(hipEventElapsedTime(find_ms, t->ev[2], t->ev[3]));
+    }
+  }
+  return BHT_OK;
+}
+
+bht_status bht_info(const bht_table* t, uint64_t* num_buckets, uint32_t* bucket_size,
+                    uint64_t* n_stored, uint64_t* table_bytes) {
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  if (num_buckets) *num_buckets = t->m;
+  if (bucket_size) *bucket_size = t->b;
+  if (n_stored) *n_stored = t->built ? t->n_stored : 0;
+  if (table_bytes) *table_bytes = t->words * sizeof(uint64_t);
+  return BHT_OK;
+}
+
+bht_status bht_download(const bht_table* t, void* host_slots) {
+  if (!t || !host_slots) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(host_slots, t->d_slots, t->words * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  return BHT_OK;
+}
+
+bht_status bht_upload(bht_table* t, const void* host_slots, uint64_t n_stored) {
+  if (!t || !host_slots) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  if (n_stored > t->m * (uint64_t)t->b) return fail(BHT_ERR_CAPACITY, "more pairs than slots");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(t->d_slots, host_slots, t->words * sizeof(uint64_t), hipMemcpyHostToDevice));
+  t->built = true;
+  t->pending = false;
+  t->n_stored = n_stored;
+  return BHT_OK;
+}
+
+bht_status bht_device_slots(const bht_table* t, void** d_slots) {
+  if (!t || !d_slots) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  *d_slots = t->d_slots;
+  return BHT_OK;
+}
+
+}  // extern "C"

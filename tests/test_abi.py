@@ -1,0 +1,85 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared
+entry point, and its host copy of the hash equals the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_entry_points():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(bht_\w+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2108_07232_amd as bht
+    lib = ctypes.CDLL(bht.LIB_PATH)
+    missing = [n for n in declared_entry_points() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_entry_points()) <= set(bht.EXPORTED)
+
+
+def test_status_strings():
+    import paper_2108_07232_amd as bht
+    assert bht.bht_status_string(bht.BHT_OK) == "ok"
+    assert "failed" in bht.bht_status_string(bht.BHT_ERR_BUILD_FAILED)
+
+
+EDGE_K = [0, 1, 2, 5, 4294967290, 4294967291, 4294967292, 4294967294, 0xFFFFFFFF, 123456789]
+EDGE_M = [1, 2, 3, 16, 72818, 18641352, 9320676, (1 << 31) - 1, 0xFFFFFFFF]
+
+
+def test_library_hash32_equals_oracle():
+    import paper_2108_07232_amd as bht
+    P = 4294967291
+    consts = [(1, 0), (P - 1, P - 1), (2, 3), (P - 1, 0), (1, P - 1)]
+    consts += list(zip(*datagen.hash_constants(4, 4)))
+    for a, c in consts:
+        for k in EDGE_K:
+            for m in EDGE_M:
+                assert bht.bht_hash32(a, c, k, m) == oracle.hash32(a, c, k, m), (a, c, k, m)
+    rng = np.random.default_rng(0)
+    for _ in range(3000):
+        a, c = int(rng.integers(1, P)), int(rng.integers(0, P))
+        k, m = int(rng.integers(0, 1 << 32)), int(rng.integers(1, 1 << 32))
+        assert bht.bht_hash32(a, c, k, m) == oracle.hash32(a, c, k, m)
+
+
+def test_library_hash64_equals_oracle():
+    import paper_2108_07232_amd as bht
+    Q = (1 << 61) - 1
+    rng = np.random.default_rng(1)
+    edge_k = [0, 1, Q - 1, Q, Q + 1, (1 << 64) - 2, (1 << 63), 0x123456789ABCDEF]
+    edge_m = [1, 2, 8, 18641352, (1 << 32) - 1, (1 << 40) + 7]
+    for a, c in [(1, 0), (Q - 1, Q - 1), (2, 3)] + list(zip(*datagen.hash_constants64(2, 3))):
+        for k in edge_k:
+            for m in edge_m:
+                assert bht.bht_hash64(a, c, k, m) == oracle.hash64(a, c, k, m), (a, c, k, m)
+    for _ in range(2000):
+        a, c = int(rng.integers(1, Q)), int(rng.integers(0, Q))
+        k = int(rng.integers(0, 1 << 63)) * 2 + int(rng.integers(0, 2))
+        m = int(rng.integers(1, 1 << 40))
+        assert bht.bht_hash64(a, c, k, m) == oracle.hash64(a, c, k, m)
+
+
+def test_product_path_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2108_07232_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                for banned in ("import oracle", "from oracle", "liboracle", "oracle.h",
+                               "import datagen", "from datagen"):
+                    assert banned not in text, (fn, banned)

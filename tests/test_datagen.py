@@ -14,10 +14,20 @@ def test_keys_unique_no_sentinel_and_seeded():
     np.testing.assert_array_equal(k[:1000], datagen.unique_keys(1000, 5))
 
 
-def test_feistel_is_a_bijection_on_a_sample():
-    x = np.arange(0, 1 << 20, dtype=np.uint32)
-    y = datagen.feistel32(x, [1, 2, 3, 4])
-    assert len(np.unique(y)) == len(x)
+def test_permutation_is_a_bijection():
+    for n in (1, 2, 3, 1000, 65536, 100003):
+        p = datagen.permutation(n, 4)
+        np.testing.assert_array_equal(np.sort(p), np.arange(n))
+    assert not np.array_equal(datagen.permutation(1000, 4), np.arange(1000))
+
+
+def test_native_splitmix_matches_published_recurrence():
+    seed = 1234567
+    ref = datagen.splitmix64(seed, 100)          # numpy statement of the recurrence
+    np.testing.assert_array_equal(datagen.splitmix64_native(seed, 100), ref)
+    np.testing.assert_array_equal(datagen.splitmix64_native(seed, 10, start=90), ref[90:])
+    # published first output of splitmix64 seeded with 0
+    assert int(datagen.splitmix64(0, 1)[0]) == 0xE220A8397B1DCDAF
 
 
 def test_negatives_disjoint_and_mixed_fraction():
@@ -27,10 +37,10 @@ def test_negatives_disjoint_and_mixed_fraction():
     assert len(np.intersect1d(keys, neg)) == 0
     assert not np.any(neg == np.uint32(0xFFFFFFFF))
     for frac in (0.0, 0.5, 1.0):
-        q = datagen.mixed_queries(keys, n, frac, 9)
+        q = datagen.mixed_queries(n, n, frac, 9)
         assert len(q) == n
         assert int(np.isin(q, keys).sum()) == int(frac * n)
-    q = datagen.positive_queries(keys, 9)
+    q = datagen.positive_queries(n, 9)
     np.testing.assert_array_equal(np.sort(q), np.sort(keys))
 
 
@@ -53,3 +63,17 @@ def test_keys64():
     assert len(np.unique(k)) == len(k) and not np.any(k == np.uint64(2**64 - 1))
     neg = datagen.negative_keys64(1000, 1 << 16, 3)
     assert len(np.intersect1d(k, neg)) == 0
+
+
+def test_queries_follow_the_key_stream():
+    n = 5000
+    keys = datagen.unique_keys(n, 3)
+    pos = datagen.positive_queries(n, 3)
+    np.testing.assert_array_equal(np.sort(pos), np.sort(keys))
+    for count, frac in [(n, 0.5), (3 * n, 0.7), (100, 0.0), (2 * n, 1.0)]:
+        q = datagen.mixed_queries(n, count, frac, 3)
+        member = np.isin(q, keys)
+        assert int(member.sum()) == int(frac * count)
+        assert len(np.unique(q[~member])) == int((~member).sum())   # distinct negatives
+    q64 = datagen.mixed_queries(n, n, 0.5, 3, wide=True)
+    assert int(np.isin(q64, datagen.unique_keys64(n, 3)).sum()) == n // 2

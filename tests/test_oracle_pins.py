@@ -236,7 +236,7 @@ def test_oracle_find_equals_brute_force(scheme, b, h, lf, n):
             continue           # a failed build is retried with new constants
         ok += 1
         assert oracle.check32(params, table, keys, vals) == (0, "ok")
-        q = datagen.mixed_queries(keys, 2 * n, 0.5, seed)
+        q = datagen.mixed_queries(n, 2 * n, 0.5, seed)
         v, f, _, _ = oracle.find32(params, table, q)
         bv, bf = oracle.brute_find32(keys, vals, q)
         np.testing.assert_array_equal(f, bf)
@@ -257,7 +257,7 @@ def test_two_level_iceberg_find_equals_brute_force():
         if st != oracle.OK:
             continue
         assert oracle.check32(params, table, keys, vals) == (0, "ok")
-        q = datagen.mixed_queries(keys, n, 0.5, seed)
+        q = datagen.mixed_queries(n, n, 0.5, seed)
         v, f, probes, per = oracle.find32(params, table, q)
         bv, bf = oracle.brute_find32(keys, vals, q)
         np.testing.assert_array_equal(f, bf)
@@ -275,7 +275,7 @@ def test_oracle_64bit_find_equals_brute_force():
         st, table, _ = oracle.build64(params, keys, vals)
         assert st == oracle.OK
         assert oracle.check64(params, table, keys, vals) == (0, "ok")
-        q = datagen.mixed_queries64(keys, 2 * n, 0.5, seed)
+        q = datagen.mixed_queries(n, 2 * n, 0.5, seed, wide=True)
         v, f, _ = oracle.find64(params, table, q)
         bv, bf = oracle.brute_find64(keys, vals, q)
         np.testing.assert_array_equal(f, bf)
@@ -437,7 +437,7 @@ def _probe_stats(scheme, n, lf, b, h=None, threshold=0, seeds=range(1, 8)):
         st, table, ins = oracle.build32(params, keys, vals)
         if st != oracle.OK:
             continue
-        pos = datagen.positive_queries(keys, seed)
+        pos = datagen.positive_queries(n, seed)
         neg = datagen.negative_keys(n, n, seed)
         _, _, pp, per_pos = oracle.find32(params, table, pos)
         _, _, pn, _ = oracle.find32(params, table, neg)
