@@ -32,10 +32,16 @@ def parse():
     ap.add_argument("--lf", type=float, default=0.9)
     ap.add_argument("--bucket", type=int, default=16)
     ap.add_argument("--tile", type=int, default=None)
+    ap.add_argument("--schedule", default="default", choices=["default", "refill", "chunk"])
+    ap.add_argument("--grid", type=int, default=0, help="blocks per launch (0 = resident)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-log2n", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--out", default=None, help="also append the JSON line to this file")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (untimed), "
+                         "the reference for scaling hardware byte counters")
     return ap.parse_args()
 
 
@@ -55,6 +61,61 @@ def algorithmic_bytes(probes):
         "find_neg": 9 + 128 * probes["neg"],
         "find_mix": 9 + 128 * probes["mix"],
     }
+
+
+def measure_ceilings(bht, table, torch, stream):
+    """Random-access ceilings on the table's own slot array (2.39 GB at the
+    default size): aligned random block reads of 32..256 bytes and slot-size
+    compare-and-swaps that never change memory."""
+    slots = bht.bht_device_slots(table.handle)
+    _, _, _, nbytes = table.info
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = {}
+    reads = 1 << 28
+    for lb in (32, 64, 128, 256):
+        bht.bht_diag_gather(slots, nbytes, reads, lb, 1, sink, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        bht.bht_diag_gather(slots, nbytes, reads, lb, 2, sink, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out["gather%d_gacc_s" % lb] = round(reads / ms / 1e6, 2)
+        out["gather%d_gbs" % lb] = round(reads * lb / ms / 1e6, 1)
+    ops = 1 << 27
+    bht.bht_diag_cas(slots, nbytes, ops, 1, sink, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    bht.bht_diag_cas(slots, nbytes, ops, 2, sink, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    out["cas_gops_s"] = round(ops / e0.elapsed_time(e1) / 1e6, 2)
+    return out
+
+
+def kernel_source_sha():
+    """SHA-256 prefix of the sources that define the build and find kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("bht_hash.hpp", "bht_kernels.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2108_07232_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "bcht_2e28_lf090_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    sha = kernel_source_sha()
+    for line in open(path):
+        if line.startswith("TRAFFIC "):
+            rec = json.loads(line[len("TRAFFIC "):])
+            if rec.get("kernels_sha256_16") == sha:
+                return rec
+    return None
 
 
 def cpu_baseline(args, n_s):
@@ -130,7 +191,7 @@ def main():
     seed_try = args.seed
     a, c = datagen.hash_constants(seed_try, 3)
     table = bht.Table(cap, args.bucket, "bcht", a, c, rng_seed=datagen.rng_seed(seed_try),
-                      tile=args.tile)
+                      tile=args.tile, find_schedule=args.schedule, grid_blocks=args.grid)
     bht.bht_enable_timing(table.handle, True)
     m, b, _, table_bytes = table.info
     stream = torch.cuda.current_stream()
@@ -174,6 +235,16 @@ def main():
             for name, ms in find_kernel_ms.items():
                 record[name].append(ms)
 
+    if args.copy_calibration_mib:
+        src = torch.empty(args.copy_calibration_mib << 18, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: %d MiB read + %d MiB written" % (args.copy_calibration_mib,
+                                                                  args.copy_calibration_mib))
     log("warmup %d steps" % args.warmup)
     for _ in range(args.warmup):
         step(None)
@@ -190,6 +261,8 @@ def main():
     # correctness spot check of the last step's mixed batch against the
     # generator's membership (positives found, negatives absent)
     found_mix = int(out_f.sum().item())
+
+    ceilings = measure_ceilings(bht, table, torch, stream) if not args.no_ceilings else None
 
     kernel_ms = {k: float(np.mean(v)) for k, v in rec.items()}
     cpu = None
@@ -212,8 +285,16 @@ def main():
     roofline = None
     if bytes_per:
         ach = kernels[dominant]["achieved_gbs"]
+        traffic = None
+        rec = recorded_traffic()
+        if rec and rec.get("n") == n and dominant in rec:
+            traffic = rec[dominant]
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": ach, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic}
+        if traffic:
+            roofline["traffic_gbs"] = round(traffic / (kernel_ms[dominant] * 1e-3) / 1e9, 1)
+        if ceilings:
+            roofline["gather128_ceiling_gbs"] = ceilings["gather128_gbs"]
 
     total_ops = args.steps * 4 * n
     result = {
@@ -242,6 +323,7 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "ceilings": ceilings,
         "probes_per_key_oracle": {k: round(v, 4) for k, v in probes.items()} if probes else None,
         "build_failures": failures,
         "mixed_found": found_mix,

@@ -140,10 +140,21 @@ bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint6
                             uint32_t* d_out_values, uint8_t* d_out_found, uint8_t* d_probes,
                             void* stream);
 
-/* Tuning: lanes per tile that read one bucket together (1 for bucket_size
- * 1; 4, 8 or 16 otherwise, at most bucket_size).  Changes speed only, never
- * results. */
-bht_status bht_set_tile(bht_table* t, uint32_t tile_width);
+/* Tuning (speed only, never results).  tile_width: lanes that read one
+ * bucket together (1 for bucket_size 1; 4, 8 or 16 otherwise, at most
+ * bucket_size; 0 keeps the default).  find_schedule: BHT_FIND_DEFAULT,
+ * BHT_FIND_REFILL (a lane that finishes a query takes the next one) or
+ * BHT_FIND_CHUNK (a wave answers 64 consecutive queries per chunk and writes
+ * their results together).  grid_blocks: blocks of 256 threads per launch,
+ * 0 = as many as the device keeps resident. */
+typedef enum { BHT_FIND_DEFAULT = 0, BHT_FIND_REFILL = 1, BHT_FIND_CHUNK = 2 } bht_find_schedule;
+typedef struct {
+  uint32_t tile_width;
+  uint32_t find_schedule;
+  uint32_t grid_blocks;
+} bht_tuning;
+bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning);
+bht_status bht_get_tuning(const bht_table* t, bht_tuning* tuning);
 
 /* Profiling: when enabled, HIP events are recorded on the call's stream
  * right before and after the main kernel of each build (the insertion
@@ -170,6 +181,18 @@ bht_status bht_upload(bht_table* t, const void* host_slots, uint64_t n_stored);
 /* Device address of the slot array (for callers that query several tables
  * in one launch). */
 bht_status bht_device_slots(const bht_table* t, void** d_slots);
+
+/* Diagnostics (ceilings for the roofline).  bht_diag_gather reads n_reads
+ * random aligned blocks of line_bytes (32, 64, 128 or 256) from d_buf
+ * (bytes long), line_bytes/16 lanes x 16 bytes per block, no table logic;
+ * with 128 it is the access pattern of one bucket probe.  bht_diag_cas issues
+ * n_ops random 8-byte compare-and-swaps on d_buf that never change it (the
+ * new value equals the expected one).  d_sink is a device uint64 the
+ * kernels may write.  Both are asynchronous on stream. */
+bht_status bht_diag_gather(const void* d_buf, uint64_t bytes, uint64_t n_reads, uint32_t line_bytes,
+                           uint64_t seed, uint64_t* d_sink, void* stream);
+bht_status bht_diag_cas(void* d_buf, uint64_t bytes, uint64_t n_ops, uint64_t seed,
+                        uint64_t* d_sink, void* stream);
 
 /* Host copy of the library's hash, for checking its arithmetic without a
  * GPU: ((a*k + b) mod p) mod m with the 32-bit family, and with the 64-bit

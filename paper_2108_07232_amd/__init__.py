@@ -45,6 +45,14 @@ class bht_params(ctypes.Structure):
     ]
 
 
+class bht_tuning(ctypes.Structure):
+    _fields_ = [("tile_width", ctypes.c_uint32), ("find_schedule", ctypes.c_uint32),
+                ("grid_blocks", ctypes.c_uint32)]
+
+
+BHT_FIND_DEFAULT, BHT_FIND_REFILL, BHT_FIND_CHUNK = 0, 1, 2
+FIND_SCHEDULES = {"default": 0, "refill": 1, "chunk": 2}
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("libbht.so is not built; run __graft_entry__.build() "
                       "(or python paper_2108_07232_amd/build.py) first")
@@ -65,7 +73,8 @@ _SIGS = {
     "bht_find64": (_st, [_p, _p, _u64, _p, _p, _p]),
     "bht_build_counted": (_st, [_p, _p, _p, _u64, _p, _p]),
     "bht_find_counted": (_st, [_p, _p, _u64, _p, _p, _p, _p]),
-    "bht_set_tile": (_st, [_p, _u32]),
+    "bht_set_tuning": (_st, [_p, ctypes.POINTER(bht_tuning)]),
+    "bht_get_tuning": (_st, [_p, ctypes.POINTER(bht_tuning)]),
     "bht_enable_timing": (_st, [_p, ctypes.c_int]),
     "bht_kernel_ms": (_st, [_p, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "bht_info": (_st, [_p, ctypes.POINTER(_u64), ctypes.POINTER(_u32), ctypes.POINTER(_u64),
@@ -73,6 +82,8 @@ _SIGS = {
     "bht_download": (_st, [_p, _p]),
     "bht_upload": (_st, [_p, _p, _u64]),
     "bht_device_slots": (_st, [_p, _pp]),
+    "bht_diag_gather": (_st, [_p, _u64, _u64, _u32, _u64, _p, _p]),
+    "bht_diag_cas": (_st, [_p, _u64, _u64, _u64, _p, _p]),
     "bht_hash32": (_u64, [_u64, _u64, _u32, _u64]),
     "bht_hash64": (_u64, [_u64, _u64, _u64, _u64]),
     "bht_status_string": (ctypes.c_char_p, [_st]),
@@ -215,8 +226,17 @@ def bht_find_counted(table, queries, out_values, out_found, probes, n=None, stre
            "bht_find_counted")
 
 
-def bht_set_tile(table, tile_width: int):
-    _check(_lib.bht_set_tile(table, tile_width), "bht_set_tile")
+def bht_set_tuning(table, tile_width: int = 0, find_schedule=0, grid_blocks: int = 0):
+    if isinstance(find_schedule, str):
+        find_schedule = FIND_SCHEDULES[find_schedule]
+    tu = bht_tuning(tile_width, find_schedule, grid_blocks)
+    _check(_lib.bht_set_tuning(table, ctypes.byref(tu)), "bht_set_tuning")
+
+
+def bht_get_tuning(table):
+    tu = bht_tuning()
+    _check(_lib.bht_get_tuning(table, ctypes.byref(tu)), "bht_get_tuning")
+    return tu.tile_width, tu.find_schedule, tu.grid_blocks
 
 
 def bht_enable_timing(table, on: bool = True):
@@ -256,6 +276,17 @@ def bht_device_slots(table) -> int:
     return out.value
 
 
+def bht_diag_gather(d_buf: int, nbytes: int, n_reads: int, line_bytes: int, seed, sink,
+                    stream=None):
+    _check(_lib.bht_diag_gather(ctypes.c_void_p(d_buf), nbytes, n_reads, line_bytes, seed,
+                                _dptr(sink, None, "sink"), _stream(stream)), "bht_diag_gather")
+
+
+def bht_diag_cas(d_buf: int, nbytes: int, n_ops: int, seed, sink, stream=None):
+    _check(_lib.bht_diag_cas(ctypes.c_void_p(d_buf), nbytes, n_ops, seed,
+                             _dptr(sink, None, "sink"), _stream(stream)), "bht_diag_cas")
+
+
 def bht_hash32(a: int, b: int, k: int, m: int) -> int:
     return int(_lib.bht_hash32(a, b, k, m))
 
@@ -275,15 +306,16 @@ class Table:
 
     def __init__(self, capacity_slots: int, bucket_size: int, scheme="bcht", a=(), b=(),
                  key_bits=32, rng_seed=0x9E3779B9, max_chain=128, iht_threshold=0,
-                 iht_secondary_b=0, iht_secondary_m=0, tile=None):
+                 iht_secondary_b=0, iht_secondary_m=0, tile=None, find_schedule=0,
+                 grid_blocks=0):
         self.params = make_params(a, b, key_bits=key_bits, rng_seed=rng_seed,
                                   max_chain=max_chain, iht_threshold=iht_threshold,
                                   iht_secondary_b=iht_secondary_b,
                                   iht_secondary_m=iht_secondary_m)
         self.key_bits = key_bits
         self.handle = bht_create(capacity_slots, bucket_size, scheme, self.params)
-        if tile is not None:
-            bht_set_tile(self.handle, tile)
+        if tile is not None or find_schedule or grid_blocks:
+            bht_set_tuning(self.handle, tile or 0, find_schedule, grid_blocks)
 
     def close(self):
         if self.handle:

@@ -10,6 +10,7 @@
 #include <unordered_map>
 
 #include "bht.h"
+#include "bht_diag.hpp"
 #include "bht_kernels.hpp"
 
 using namespace bht;
@@ -21,6 +22,8 @@ struct bht_table {
   uint32_t key_bits;
   bht_params params;
   uint32_t tile;        // lanes per tile reading one bucket
+  uint32_t find_schedule;
+  uint32_t grid_blocks; // 0 = resident capacity
   uint64_t* d_slots;
   uint64_t words;       // uint64 words in the slot array
   uint32_t* d_status;   // [0] flags
@@ -59,7 +62,11 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Blocks to launch: enough to give every lane an item, capped at what the
 // device keeps resident at once (the kernels loop over their share).
-int grid_for(const void* kernel, uint64_t items) {
+// items_per_lane > 0 asks for at least ceil(items / (256 * items_per_lane))
+// blocks even beyond the resident count: short per-wave ranges let the
+// dispatcher balance waves that finish at different times.
+int grid_for(const void* kernel, uint64_t items, uint32_t fixed = 0, uint64_t items_per_lane = 0) {
+  if (fixed) return (int)fixed;
   static std::mutex mu;
   static std::unordered_map<const void*, int> resident;
   int cap;
@@ -78,7 +85,11 @@ int grid_for(const void* kernel, uint64_t items) {
     }
   }
   uint64_t want = (items + kBlock - 1) / kBlock;
-  return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)cap));
+  uint64_t grid = std::min<uint64_t>(want, (uint64_t)cap);
+  if (items_per_lane)
+    grid = std::max<uint64_t>(grid, std::min<uint64_t>(
+        (items + kBlock * items_per_lane - 1) / (kBlock * items_per_lane), 1u << 20));
+  return (int)std::max<uint64_t>(1, grid);
 }
 
 Hash32 make_hash32(const bht_params& p, uint64_t m, uint32_t h) {
@@ -135,16 +146,22 @@ struct Kern {
   static constexpr BuildKernel build(bool count) {
     return count ? cuckoo_build_kernel<B, W, true> : cuckoo_build_kernel<B, W, false>;
   }
-  static constexpr FindKernel find(bool count) {
+  static constexpr FindKernel find(bool count, uint32_t schedule) {
+    if (schedule == BHT_FIND_CHUNK)
+      return count ? cuckoo_find_chunk_kernel<B, W, true> : cuckoo_find_chunk_kernel<B, W, false>;
     return count ? cuckoo_find_kernel<B, W, true> : cuckoo_find_kernel<B, W, false>;
   }
 };
 
-bool pick_cuckoo(uint32_t b, uint32_t w, bool count, BuildKernel* bk, FindKernel* fk) {
+constexpr uint32_t kDefaultSchedule = BHT_FIND_CHUNK;
+
+bool pick_cuckoo(uint32_t b, uint32_t w, bool count, BuildKernel* bk, FindKernel* fk,
+                 uint32_t schedule = kDefaultSchedule) {
+  if (schedule == BHT_FIND_DEFAULT) schedule = kDefaultSchedule;
 #define BHT_CASE(B_, W_)                       \
   if (b == B_ && w == W_) {                    \
     *bk = Kern<B_, W_>::build(count);          \
-    *fk = Kern<B_, W_>::find(count);           \
+    *fk = Kern<B_, W_>::find(count, schedule); \
     return true;                               \
   }
   BHT_CASE(1, 1)
@@ -193,7 +210,7 @@ bht_status build32_enqueue(bht_table* t, const uint32_t* keys, const uint32_t* v
     g.H = make_hash32(t->params, t->m, t->params.num_hashes);
     g.max_chain = t->params.max_chain;
     g.rng_seed = t->params.rng_seed;
-    const int grid = grid_for((const void*)bk, n);
+    const int grid = grid_for((const void*)bk, n, t->grid_blocks);
     if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
     bk<<<grid, kBlock, 0, st>>>(g);
     HIP_TRY(hipGetLastError());
@@ -214,7 +231,7 @@ bht_status find32_enqueue(const bht_table* t, const uint32_t* q, uint64_t n, uin
   if (!q || !out_v || !out_f) return fail(BHT_ERR_INVALID_ARG, "null query or output pointer");
   BuildKernel bk;
   FindKernel fk;
-  if (!pick_cuckoo(t->b, t->tile, probes != nullptr, &bk, &fk))
+  if (!pick_cuckoo(t->b, t->tile, probes != nullptr, &bk, &fk, t->find_schedule))
     return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
   FindArgs32 g;
   g.slots = t->d_slots;
@@ -224,7 +241,8 @@ bht_status find32_enqueue(const bht_table* t, const uint32_t* q, uint64_t n, uin
   g.out_f = out_f;
   g.probes = probes;
   g.H = make_hash32(t->params, t->m, t->params.num_hashes);
-  const int grid = grid_for((const void*)fk, n);
+  const uint32_t sched = t->find_schedule ? t->find_schedule : kDefaultSchedule;
+  const int grid = grid_for((const void*)fk, n, t->grid_blocks, sched == BHT_FIND_CHUNK ? 16 : 0);
   bht_table* mt = const_cast<bht_table*>(t);
   if (t->timing) HIP_TRY(hipEventRecord(t->ev[2], as_stream(stream)));
   fk<<<grid, kBlock, 0, as_stream(stream)>>>(g);
@@ -386,13 +404,25 @@ bht_status bht_find64(const bht_table* t, const uint64_t* d_queries, uint64_t n,
   return fail(BHT_ERR_UNSUPPORTED, "64-bit keys not available in this build");
 }
 
-bht_status bht_set_tile(bht_table* t, uint32_t tile_width) {
-  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning) {
+  if (!t || !tuning) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  const uint32_t w = tuning->tile_width ? tuning->tile_width : t->tile;
+  if (tuning->find_schedule > BHT_FIND_CHUNK) return fail(BHT_ERR_INVALID_ARG, "bad schedule");
   BuildKernel bk;
   FindKernel fk;
-  if (!pick_cuckoo(t->b, tile_width, false, &bk, &fk))
+  if (!pick_cuckoo(t->b, w, false, &bk, &fk, tuning->find_schedule))
     return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
-  t->tile = tile_width;
+  t->tile = w;
+  t->find_schedule = tuning->find_schedule;
+  t->grid_blocks = tuning->grid_blocks;
+  return BHT_OK;
+}
+
+bht_status bht_get_tuning(const bht_table* t, bht_tuning* tuning) {
+  if (!t || !tuning) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  tuning->tile_width = t->tile;
+  tuning->find_schedule = t->find_schedule;
+  tuning->grid_blocks = t->grid_blocks;
   return BHT_OK;
 }
 
@@ -456,6 +486,41 @@ bht_status bht_upload(bht_table* t, const void* host_slots, uint64_t n_stored) {
 bht_status bht_device_slots(const bht_table* t, void** d_slots) {
   if (!t || !d_slots) return fail(BHT_ERR_INVALID_ARG, "null argument");
   *d_slots = t->d_slots;
+  return BHT_OK;
+}
+
+bht_status bht_diag_gather(const void* d_buf, uint64_t bytes, uint64_t n_reads, uint32_t line_bytes,
+                           uint64_t seed, uint64_t* d_sink, void* stream) {
+  if (!d_buf || !d_sink) return fail(BHT_ERR_INVALID_ARG, "null pointer");
+  if (line_bytes != 32 && line_bytes != 64 && line_bytes != 128 && line_bytes != 256)
+    return fail(BHT_ERR_INVALID_ARG, "line_bytes must be 32, 64, 128 or 256");
+  if (bytes < line_bytes) return fail(BHT_ERR_INVALID_ARG, "buffer smaller than one line");
+  const uint64_t* buf = static_cast<const uint64_t*>(d_buf);
+  auto sink = reinterpret_cast<unsigned long long*>(d_sink);
+  hipStream_t st = as_stream(stream);
+  const uint64_t units = bytes / line_bytes;
+#define BHT_GATHER(LB)                                                              \
+  if (line_bytes == LB) {                                                           \
+    const int grid = grid_for((const void*)diag_gather_kernel<LB>, 1ull << 40);     \
+    diag_gather_kernel<LB><<<grid, kBlock, 0, st>>>(buf, units, n_reads, seed, sink); \
+  }
+  BHT_GATHER(32)
+  BHT_GATHER(64)
+  BHT_GATHER(128)
+  BHT_GATHER(256)
+#undef BHT_GATHER
+  HIP_TRY(hipGetLastError());
+  return BHT_OK;
+}
+
+bht_status bht_diag_cas(void* d_buf, uint64_t bytes, uint64_t n_ops, uint64_t seed,
+                        uint64_t* d_sink, void* stream) {
+  if (!d_buf || !d_sink || bytes < 8) return fail(BHT_ERR_INVALID_ARG, "bad buffer");
+  const int grid = grid_for((const void*)diag_cas_kernel, 1ull << 40);
+  diag_cas_kernel<<<grid, kBlock, 0, as_stream(stream)>>>(
+      static_cast<uint64_t*>(d_buf), bytes / 8, n_ops, seed,
+      reinterpret_cast<unsigned long long*>(d_sink));
+  HIP_TRY(hipGetLastError());
   return BHT_OK;
 }
 

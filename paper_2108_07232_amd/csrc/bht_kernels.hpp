@@ -170,6 +170,127 @@ __global__ void fill_empty_kernel(uint64_t* __restrict__ slots, uint64_t words,
   if ((words & 1) && gtid == 0) slots[words - 1] = kEmptyPair;
 }
 
+// ----------------------------------------------------------- input feed
+
+// A wave consumes its range in order.  Lane i holds item base+i of chunk A
+// and item base+64+i of chunk B in registers; lanes that need work take the
+// next items by rank (one crossbar read each) and, once chunk A is used up,
+// chunk B becomes A and the following chunk is loaded.  That load is needed
+// one chunk later, so refilling a lane never waits on memory.
+template <typename T>
+struct Feed {
+  const T* src;
+  uint64_t base, cursor, end;
+  T a, b;
+
+  __device__ __forceinline__ void init(const T* s, Range r, T fill) {
+    const uint32_t lane = __lane_id();
+    src = s;
+    base = cursor = r.cursor;
+    end = r.end;
+    a = (base + lane < end) ? src[base + lane] : fill;
+    b = (base + 64 + lane < end) ? src[base + 64 + lane] : fill;
+  }
+
+  // Offset of this lane's new item within the two chunks, or -1 if none.
+  __device__ __forceinline__ int64_t claim(bool need, uint64_t* idx) {
+    const uint64_t nm = ballot(need);
+    const uint64_t take = cursor + lanes_below(nm);
+    *idx = take;
+    const uint64_t taken = (uint64_t)__popcll(nm);
+    const int64_t off = (need && take < end) ? (int64_t)(take - base) : -1;
+    last_reads_b = cursor + taken > base + 64;
+    cursor = cursor + taken < end ? cursor + taken : end;
+    return off;
+  }
+
+  __device__ __forceinline__ T value_at(int64_t off) const {
+    const uint32_t src_lane = (uint32_t)off & 63u;
+    T x = (T)shfl32((uint32_t)a, src_lane);
+    if (last_reads_b) {  // wave-uniform: some lane reads chunk B
+      const T y = (T)shfl32((uint32_t)b, src_lane);
+      if (off >= 64) x = y;
+    }
+    return x;
+  }
+
+  // After every value_at of this round: retire chunk A once it is used up.
+  __device__ __forceinline__ void advance(T fill) {
+    if (cursor >= base + 64) {
+      const uint32_t lane = __lane_id();
+      base += 64;
+      a = b;
+      b = (base + 64 + lane < end) ? src[base + 64 + lane] : fill;
+    }
+  }
+
+  bool last_reads_b = false;
+};
+
+// Tile-cooperative read of the buckets of the lanes in `mask`: slice j holds
+// this lane's part (slots [lt*S, lt*S+S)) of the bucket of tile lane j.
+template <int B, int W>
+__device__ __forceinline__ void tile_read(const uint64_t* __restrict__ slots, uint32_t bucket,
+                                          uint64_t mask, uint32_t tb, uint32_t lt,
+                                          Part<B / W> (&d)[W]) {
+  constexpr int S = B / W;
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    const uint32_t bj = shfl32(bucket, tb + j);
+    if ((mask >> (tb + j)) & 1ull) d[j] = load_part<S>(slots + (uint64_t)bj * B + lt * S);
+    else d[j] = empty_part<S>();
+  }
+}
+
+// Listing 2 for the bucket of every tile lane j: hit = some slot holds q_j
+// (value = that slot's value), room = some slot is empty.  Each lane gets
+// the answer for its own bucket.
+template <int B, int W>
+__device__ __forceinline__ void tile_match(const Part<B / W> (&d)[W], uint32_t q, uint32_t tb,
+                                           uint32_t lt, bool* hit, bool* room, uint32_t* value) {
+  constexpr int S = B / W;
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    const uint32_t qj = shfl32(q, tb + j);
+    bool m = false, e = false;
+    uint32_t vsel = kEmptyKey;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t k = (uint32_t)d[j].s[s];
+      if (k == qj) {
+        m = true;
+        vsel = (uint32_t)(d[j].s[s] >> 32);
+      }
+      e |= (k == kEmptyKey);
+    }
+    const uint64_t hm = tile_bits<W>(ballot(m), tb);
+    const uint64_t em = tile_bits<W>(ballot(e), tb);
+    const uint32_t src = tb + (hm ? (uint32_t)__builtin_ctzll(hm) : 0u);
+    const uint32_t v = shfl32(vsel, src);
+    if (lt == (uint32_t)j) {
+      *hit = hm != 0;
+      *room = em != 0;
+      *value = v;
+    }
+  }
+}
+
+// Listing 2 compute_load for the bucket of every tile lane j.
+template <int B, int W>
+__device__ __forceinline__ uint32_t tile_load(const Part<B / W> (&d)[W], uint32_t tb, uint32_t lt) {
+  constexpr int S = B / W;
+  uint32_t load = 0;
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      cnt += __popcll(tile_bits<W>(ballot((uint32_t)d[j].s[s] != kEmptyKey), tb));
+    if (lt == (uint32_t)j) load = cnt;
+  }
+  return load;
+}
+
 // ------------------------------------------------------- cuckoo (BCHT)
 
 struct BuildArgs32 {
@@ -199,61 +320,49 @@ enum : uint32_t { kRead = 0, kWalk = 1, kEvict = 2 };
 // Bucketed cuckoo insertion (Section III-A, Section V-B) for every pair.
 template <int B, int W, bool COUNT>
 __global__ __launch_bounds__(kBlock) void cuckoo_build_kernel(BuildArgs32 g) {
-  constexpr int S = B / W;
   const uint32_t lane = __lane_id();
   const uint32_t tb = lane & ~(uint32_t)(W - 1);
   const uint32_t lt = lane & (uint32_t)(W - 1);
-  Range r = wave_range(g.n);
+  const Range r = wave_range(g.n);
   const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t rng = g.rng_seed ^ (uint32_t)(gtid * 0x9E3779B9ull) ^ (uint32_t)(gtid >> 32);
   if (rng == 0) rng = 0x2545F491u;
 
+  Feed<uint32_t> fk, fv;
+  fk.init(g.keys, r, kEmptyKey);
+  fv.init(g.vals, r, 0u);
   bool active = false;
   uint32_t key = 0, val = 0, bucket = 0, chain = 0, slot = 0, phase = kRead;
   uint32_t probes = 0, flags = 0;
 
   for (;;) {
-    // Lanes without work take the next items of the wave's range, in lane
-    // order, so the refill is one coalesced load.
-    const uint64_t need = ballot(!active);
-    const uint64_t take = r.cursor + lanes_below(need);
-    if (!active && take < r.end) {
-      key = g.keys[take];
-      val = g.vals[take];
-      if (key == kEmptyKey) {
+    uint64_t idx;
+    const int64_t off = fk.claim(!active, &idx);
+    fv.claim(!active, &idx);
+    const uint32_t k_new = fk.value_at(off);
+    const uint32_t v_new = fv.value_at(off);
+    fk.advance(kEmptyKey);
+    fv.advance(0u);
+    if (off >= 0) {
+      if (k_new == kEmptyKey) {
         flags |= kFlagSentinel;
       } else {
         active = true;
+        key = k_new;
+        val = v_new;
         bucket = hash32(g.H, 0, key);
         chain = 0;
         phase = kRead;
       }
     }
-    r.cursor = r.cursor + __popcll(need) < r.end ? r.cursor + __popcll(need) : r.end;
     if (ballot(active) == 0) {
-      if (r.cursor >= r.end) break;
+      if (fk.cursor >= fk.end) break;
       continue;
     }
 
-    // The tile reads the bucket of each of its lanes that needs one.
-    const uint64_t rd = ballot(active && phase == kRead);
-    Part<S> d[W];
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const uint32_t bj = shfl32(bucket, tb + j);
-      if ((rd >> (tb + j)) & 1ull) d[j] = load_part<S>(g.slots + (uint64_t)bj * B + lt * S);
-      else d[j] = empty_part<S>();
-    }
-    // Listing 2 compute_load: population count of non-empty slots.
-    uint32_t load = 0;
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-      uint32_t cnt = 0;
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-        cnt += __popcll(tile_bits<W>(ballot((uint32_t)d[j].s[s] != kEmptyKey), tb));
-      if (lt == (uint32_t)j) load = cnt;
-    }
+    Part<B / W> d[W];
+    tile_read<B, W>(g.slots, bucket, ballot(active && phase == kRead), tb, lt, d);
+    const uint32_t load = tile_load<B, W>(d, tb, lt);
 
     if (active && phase == kRead) {
       if (COUNT) ++probes;
@@ -297,24 +406,28 @@ __global__ __launch_bounds__(kBlock) void cuckoo_build_kernel(BuildArgs32 g) {
 
 // Bucketed cuckoo query (Section V-B): probe H0, H1, ... in order; stop on a
 // hit, or with a miss after a bucket that lacks the key and has room.
+// Lanes that finish take new queries from the feed (refill schedule).
 template <int B, int W, bool COUNT>
 __global__ __launch_bounds__(kBlock) void cuckoo_find_kernel(FindArgs32 g) {
-  constexpr int S = B / W;
   const uint32_t lane = __lane_id();
   const uint32_t tb = lane & ~(uint32_t)(W - 1);
   const uint32_t lt = lane & (uint32_t)(W - 1);
-  Range r = wave_range(g.n);
+  const Range r = wave_range(g.n);
 
+  Feed<uint32_t> fq;
+  fq.init(g.queries, r, kEmptyKey);
   bool active = false;
   uint64_t idx = 0;
   uint32_t q = 0, round = 0, bucket = 0;
 
   for (;;) {
-    const uint64_t need = ballot(!active);
-    const uint64_t take = r.cursor + lanes_below(need);
-    if (!active && take < r.end) {
+    uint64_t take;
+    const int64_t off = fq.claim(!active, &take);
+    const uint32_t q_new = fq.value_at(off);
+    fq.advance(kEmptyKey);
+    if (off >= 0) {
       idx = take;
-      q = g.queries[idx];
+      q = q_new;
       if (q == kEmptyKey) {
         g.out_v[idx] = kEmptyKey;
         g.out_f[idx] = 0;
@@ -325,46 +438,17 @@ __global__ __launch_bounds__(kBlock) void cuckoo_find_kernel(FindArgs32 g) {
         bucket = hash32(g.H, 0, q);
       }
     }
-    r.cursor = r.cursor + __popcll(need) < r.end ? r.cursor + __popcll(need) : r.end;
     const uint64_t act = ballot(active);
     if (act == 0) {
-      if (r.cursor >= r.end) break;
+      if (fq.cursor >= fq.end) break;
       continue;
     }
 
-    Part<S> d[W];
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const uint32_t bj = shfl32(bucket, tb + j);
-      if ((act >> (tb + j)) & 1ull) d[j] = load_part<S>(g.slots + (uint64_t)bj * B + lt * S);
-      else d[j] = empty_part<S>();
-    }
+    Part<B / W> d[W];
+    tile_read<B, W>(g.slots, bucket, act, tb, lt, d);
     bool hit = false, room = false;
     uint32_t value = kEmptyKey;
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const uint32_t qj = shfl32(q, tb + j);
-      bool m = false, e = false;
-      uint32_t vsel = kEmptyKey;
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const uint32_t k = (uint32_t)d[j].s[s];
-        if (k == qj) {
-          m = true;
-          vsel = (uint32_t)(d[j].s[s] >> 32);
-        }
-        e |= (k == kEmptyKey);
-      }
-      const uint64_t hm = tile_bits<W>(ballot(m), tb);
-      const uint64_t em = tile_bits<W>(ballot(e), tb);
-      const uint32_t src = tb + (hm ? (uint32_t)__builtin_ctzll(hm) : 0u);
-      const uint32_t v = shfl32(vsel, src);
-      if (lt == (uint32_t)j) {
-        hit = hm != 0;
-        room = em != 0;
-        value = v;
-      }
-    }
+    tile_match<B, W>(d, q, tb, lt, &hit, &room, &value);
     if (active) {
       bool done = true;
       if (hit) {
@@ -383,6 +467,53 @@ __global__ __launch_bounds__(kBlock) void cuckoo_find_kernel(FindArgs32 g) {
         ++round;
         bucket = hash32_dyn(g.H, round, q);
       }
+    }
+  }
+}
+
+// Same query, chunk schedule: a wave answers 64 consecutive queries per
+// chunk in up to h rounds (round i probes H_i for the queries still open),
+// then writes the 64 results with one coalesced store each; the next
+// chunk's queries are loaded while the current chunk is probed.
+template <int B, int W, bool COUNT>
+__global__ __launch_bounds__(kBlock) void cuckoo_find_chunk_kernel(FindArgs32 g) {
+  const uint32_t lane = __lane_id();
+  const uint32_t tb = lane & ~(uint32_t)(W - 1);
+  const uint32_t lt = lane & (uint32_t)(W - 1);
+  const Range r = wave_range(g.n);
+  uint32_t q_next = (r.cursor + lane < r.end) ? g.queries[r.cursor + lane] : kEmptyKey;
+  for (uint64_t base = r.cursor; base < r.end; base += 64) {
+    const uint64_t idx = base + lane;
+    const bool valid = idx < r.end;
+    const uint32_t q = q_next;
+    q_next = (base + 64 + lane < r.end) ? g.queries[base + 64 + lane] : kEmptyKey;
+    bool open = valid && q != kEmptyKey;
+    uint32_t out = kEmptyKey, rounds = 0;
+    uint8_t found = 0;
+    for (uint32_t round = 0; round < g.H.h; ++round) {
+      const uint64_t om = ballot(open);
+      if (om == 0) break;
+      const uint32_t bucket = open ? hash32_dyn(g.H, round, q) : 0u;
+      Part<B / W> d[W];
+      tile_read<B, W>(g.slots, bucket, om, tb, lt, d);
+      bool hit = false, room = false;
+      uint32_t value = kEmptyKey;
+      tile_match<B, W>(d, q, tb, lt, &hit, &room, &value);
+      if (open) {
+        rounds = round + 1;
+        if (hit) {
+          out = value;
+          found = 1;
+          open = false;
+        } else if (room) {
+          open = false;
+        }
+      }
+    }
+    if (valid) {
+      g.out_v[idx] = out;
+      g.out_f[idx] = found;
+      if (COUNT) g.probes[idx] = (uint8_t)rounds;
     }
   }
 }

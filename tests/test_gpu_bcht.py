@@ -19,9 +19,10 @@ def bht():
     return paper_2108_07232_amd
 
 
-def gpu_table(params: oracle.Params, tile=None):
+def gpu_table(params: oracle.Params, tile=None, schedule=0):
     t = bht().Table(params.m * params.b, params.b, params.scheme, params.a, params.c,
-                    rng_seed=params.rng_seed, max_chain=params.max_chain, tile=tile)
+                    rng_seed=params.rng_seed, max_chain=params.max_chain, tile=tile,
+                    find_schedule=schedule)
     return t
 
 
@@ -54,12 +55,13 @@ def build_with_retries(scheme, n, lf, b, seed0, h=None, tile=None, tries=8):
 
 # -------------------------------------------- find on oracle-built layouts
 
+@pytest.mark.parametrize("schedule", ["refill", "chunk"])
 @pytest.mark.parametrize("b,tile,n,lf", [
     (16, 8, 1 << 20, 0.9), (16, 4, 5000, 0.95), (16, 16, 4097, 0.9), (8, 8, 3001, 0.85),
     (8, 4, 777, 0.9), (32, 16, 6000, 0.95), (32, 8, 1000, 0.9), (4, 4, 2000, 0.8),
     (1, 1, 3000, 0.8),
 ])
-def test_find_on_oracle_layout(b, tile, n, lf):
+def test_find_on_oracle_layout(b, tile, n, lf, schedule):
     scheme = "cht1" if b == 1 else "bcht"
     keys, vals = workload(n, 21)
     for s in range(10):
@@ -68,7 +70,7 @@ def test_find_on_oracle_layout(b, tile, n, lf):
         if st == oracle.OK:
             break
     assert st == oracle.OK
-    t = gpu_table(params, tile)
+    t = gpu_table(params, tile, schedule)
     t.upload(layout, n)
     for frac in (1.0, 0.5, 0.0):
         q = datagen.mixed_queries(n, n, frac, 21)
@@ -189,11 +191,13 @@ def test_reseed_after_failure_and_zero_chain():
 
 # ---------------------------------------------------------- probe counters
 
-def test_find_probe_counts_equal_oracle_on_gpu_layout():
+@pytest.mark.parametrize("schedule", ["refill", "chunk"])
+def test_find_probe_counts_equal_oracle_on_gpu_layout(schedule):
     import torch
     B = bht()
     n = 1 << 18
     t, params, keys, vals = build_with_retries("bcht", n, 0.95, 16, 4)
+    B.bht_set_tuning(t.handle, 0, schedule)
     layout = t.download()
     for frac in (1.0, 0.5, 0.0):
         q = datagen.mixed_queries(n, n, frac, 4)
