@@ -12,6 +12,7 @@
 #include "bht.h"
 #include "bht_diag.hpp"
 #include "bht_kernels.hpp"
+#include "bht_schemes.hpp"
 
 using namespace bht;
 
@@ -26,6 +27,7 @@ struct bht_table {
   uint32_t grid_blocks; // 0 = resident capacity
   uint64_t* d_slots;
   uint64_t words;       // uint64 words in the slot array
+  uint64_t slots;       // pair capacity (both levels)
   uint32_t* d_status;   // [0] flags
   uint32_t* h_status;   // pinned host copy
   uint64_t n_stored;
@@ -120,13 +122,27 @@ bool valid_params(const bht_params& p, bht_scheme scheme, uint32_t b, std::strin
     case BHT_CHT1:
       if (b != 1 || p.key_bits != 32) return *why = "CHT1 needs bucket_size 1, 32-bit keys", false;
       break;
+    case BHT_BP2HT:
+      if (p.key_bits != 32 || p.num_hashes != 2 || (b != 8 && b != 16 && b != 32))
+        return *why = "BP2HT needs 32-bit keys, 2 hashes and bucket size 8, 16 or 32", false;
+      break;
+    case BHT_IHT:
+      if (p.key_bits != 32 || p.num_hashes != 3 || (b != 16 && b != 32))
+        return *why = "IHT needs 32-bit keys, 3 hashes and bucket size 16 or 32", false;
+      if (p.iht_secondary_b != 0 && p.iht_secondary_b != 8)
+        return *why = "IHT secondary buckets hold 8 slots (or 0 for one level)", false;
+      if (p.iht_secondary_b && (p.iht_secondary_m == 0 || p.iht_secondary_m > 0xFFFFFFFFull))
+        return *why = "IHT secondary bucket count must be 1 .. 2^32 - 1", false;
+      if (p.iht_threshold > b) return *why = "IHT threshold exceeds the bucket size", false;
+      break;
     default:
-      return *why = "scheme not available in this build", false;
+      return *why = "unknown scheme", false;
   }
   return true;
 }
 
-uint32_t default_tile(uint32_t b) {
+uint32_t default_tile(bht_scheme scheme, uint32_t b) {
+  (void)scheme;
   switch (b) {
     case 1: return 1;
     case 4: return 4;
@@ -138,43 +154,74 @@ uint32_t default_tile(uint32_t b) {
 
 // --------------------------------------------------------------- dispatch
 
-using BuildKernel = void (*)(BuildArgs32);
-using FindKernel = void (*)(FindArgs32);
+enum class Kind { Cuckoo, P2, Iceberg };
 
-template <int B, int W>
-struct Kern {
-  static constexpr BuildKernel build(bool count) {
-    return count ? cuckoo_build_kernel<B, W, true> : cuckoo_build_kernel<B, W, false>;
-  }
-  static constexpr FindKernel find(bool count, uint32_t schedule) {
-    if (schedule == BHT_FIND_CHUNK)
-      return count ? cuckoo_find_chunk_kernel<B, W, true> : cuckoo_find_chunk_kernel<B, W, false>;
-    return count ? cuckoo_find_kernel<B, W, true> : cuckoo_find_kernel<B, W, false>;
-  }
+// The kernels of one table configuration (bucket size, secondary bucket
+// size, tile width, probe counting, query schedule).
+struct KernelSet {
+  Kind kind;
+  const void* build;
+  const void* find;
+  bool chunk;  // the query kernel uses the chunk schedule
 };
 
 constexpr uint32_t kDefaultSchedule = BHT_FIND_CHUNK;
 
-bool pick_cuckoo(uint32_t b, uint32_t w, bool count, BuildKernel* bk, FindKernel* fk,
-                 uint32_t schedule = kDefaultSchedule) {
-  if (schedule == BHT_FIND_DEFAULT) schedule = kDefaultSchedule;
-#define BHT_CASE(B_, W_)                       \
-  if (b == B_ && w == W_) {                    \
-    *bk = Kern<B_, W_>::build(count);          \
-    *fk = Kern<B_, W_>::find(count, schedule); \
-    return true;                               \
-  }
-  BHT_CASE(1, 1)
-  BHT_CASE(4, 4)
-  BHT_CASE(8, 4)
-  BHT_CASE(8, 8)
-  BHT_CASE(16, 4)
-  BHT_CASE(16, 8)
-  BHT_CASE(16, 16)
-  BHT_CASE(32, 8)
-  BHT_CASE(32, 16)
+template <int B, int W, bool C>
+KernelSet cuckoo_set(uint32_t schedule) {
+  const bool chunk = schedule == BHT_FIND_CHUNK;
+  return {Kind::Cuckoo, (const void*)cuckoo_build_kernel<B, W, C>,
+          chunk ? (const void*)cuckoo_find_chunk_kernel<B, W, C>
+                : (const void*)cuckoo_find_kernel<B, W, C>,
+          chunk};
+}
+
+template <int B, int W, bool C>
+KernelSet p2_set() {
+  return {Kind::P2, (const void*)p2_build_kernel<B, W, C>,
+          (const void*)stable_find_chunk_kernel<B, 0, W, C>, true};
+}
+
+template <int B, int B2, int W, bool C>
+KernelSet iceberg_set() {
+  return {Kind::Iceberg, (const void*)iceberg_build_kernel<B, B2, W, C>,
+          (const void*)stable_find_chunk_kernel<B, B2, W, C>, true};
+}
+
+template <bool C>
+bool pick_t(bht_scheme scheme, uint32_t b, uint32_t b2, uint32_t w, uint32_t schedule,
+            KernelSet* ks) {
+  if (scheme == BHT_BCHT || scheme == BHT_CHT1) {
+#define BHT_CASE(B_, W_) \
+  if (b == B_ && w == W_) return *ks = cuckoo_set<B_, W_, C>(schedule), true;
+    BHT_CASE(1, 1)
+    BHT_CASE(4, 4)
+    BHT_CASE(8, 4)
+    BHT_CASE(8, 8)
+    BHT_CASE(16, 4)
+    BHT_CASE(16, 8)
+    BHT_CASE(16, 16)
+    BHT_CASE(32, 8)
+    BHT_CASE(32, 16)
 #undef BHT_CASE
+  } else if (scheme == BHT_BP2HT) {
+    if (b == 8 && w == 8) return *ks = p2_set<8, 8, C>(), true;
+    if (b == 16 && w == 8) return *ks = p2_set<16, 8, C>(), true;
+    if (b == 32 && w == 16) return *ks = p2_set<32, 16, C>(), true;
+  } else if (scheme == BHT_IHT) {
+    if (b == 16 && b2 == 0 && w == 8) return *ks = iceberg_set<16, 0, 8, C>(), true;
+    if (b == 16 && b2 == 8 && w == 8) return *ks = iceberg_set<16, 8, 8, C>(), true;
+    if (b == 32 && b2 == 0 && w == 16) return *ks = iceberg_set<32, 0, 16, C>(), true;
+    if (b == 32 && b2 == 8 && w == 16) return *ks = iceberg_set<32, 8, 16, C>(), true;
+  }
   return false;
+}
+
+bool pick(const bht_table* t, uint32_t w, uint32_t schedule, bool count, KernelSet* ks) {
+  if (schedule == BHT_FIND_DEFAULT) schedule = kDefaultSchedule;
+  const uint32_t b2 = t->scheme == BHT_IHT ? t->params.iht_secondary_b : 0;
+  return count ? pick_t<true>(t->scheme, t->b, b2, w, schedule, ks)
+               : pick_t<false>(t->scheme, t->b, b2, w, schedule, ks);
 }
 
 bht_status launch_fill(bht_table* t, hipStream_t st) {
@@ -185,34 +232,66 @@ bht_status launch_fill(bht_table* t, hipStream_t st) {
   return BHT_OK;
 }
 
+uint64_t* secondary_slots(const bht_table* t) {
+  if (t->scheme != BHT_IHT || t->params.iht_secondary_b == 0) return nullptr;
+  return t->d_slots + t->m * t->b;
+}
+
+Hash32 secondary_hash(const bht_table* t) {
+  const uint64_t m2 = t->params.iht_secondary_b ? t->params.iht_secondary_m : t->m;
+  return make_hash32(t->params, m2, t->params.num_hashes);
+}
+
 bht_status build32_enqueue(bht_table* t, const uint32_t* keys, const uint32_t* vals, uint64_t n,
                            unsigned long long* probe_total, void* stream) {
   if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
   if (t->key_bits != 32) return fail(BHT_ERR_INVALID_ARG, "table holds 64-bit keys");
-  if (n > t->m * (uint64_t)t->b) return fail(BHT_ERR_CAPACITY, "more pairs than slots");
+  if (n > t->slots) return fail(BHT_ERR_CAPACITY, "more pairs than slots");
   if (n && (!keys || !vals)) return fail(BHT_ERR_INVALID_ARG, "null key or value pointer");
-  BuildKernel bk;
-  FindKernel fk;
-  if (!pick_cuckoo(t->b, t->tile, probe_total != nullptr, &bk, &fk))
+  KernelSet ks;
+  if (!pick(t, t->tile, t->find_schedule, probe_total != nullptr, &ks))
     return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
   hipStream_t st = as_stream(stream);
   t->built = false;
   bht_status s = launch_fill(t, st);
   if (s != BHT_OK) return s;
   if (n) {
-    BuildArgs32 g;
-    g.slots = t->d_slots;
-    g.keys = keys;
-    g.vals = vals;
-    g.n = n;
-    g.status = t->d_status;
-    g.probe_total = probe_total;
-    g.H = make_hash32(t->params, t->m, t->params.num_hashes);
-    g.max_chain = t->params.max_chain;
-    g.rng_seed = t->params.rng_seed;
-    const int grid = grid_for((const void*)bk, n, t->grid_blocks);
+    // Load-balanced placements (power of two, iceberg) decide from bucket
+    // loads read before the lane's CAS; with every pair of a small table in
+    // flight at once those loads would all be stale.  Giving each lane at
+    // least 32 pairs keeps the pairs in flight under ~3% of the table, so
+    // placement matches the serial rule; large tables still fill the device.
+    const uint64_t grid_items = ks.kind == Kind::Cuckoo ? n : (n + 31) / 32;
+    const int grid = grid_for(ks.build, grid_items, t->grid_blocks);
     if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
-    bk<<<grid, kBlock, 0, st>>>(g);
+    if (ks.kind == Kind::Cuckoo) {
+      BuildArgs32 g;
+      g.slots = t->d_slots;
+      g.keys = keys;
+      g.vals = vals;
+      g.n = n;
+      g.status = t->d_status;
+      g.probe_total = probe_total;
+      g.H = make_hash32(t->params, t->m, t->params.num_hashes);
+      g.max_chain = t->params.max_chain;
+      g.rng_seed = t->params.rng_seed;
+      reinterpret_cast<void (*)(BuildArgs32)>(const_cast<void*>(ks.build))
+          <<<grid, kBlock, 0, st>>>(g);
+    } else {
+      SchemeArgs32 g;
+      g.slots = t->d_slots;
+      g.slots2 = secondary_slots(t);
+      g.keys = keys;
+      g.vals = vals;
+      g.n = n;
+      g.status = t->d_status;
+      g.probe_total = probe_total;
+      g.H = make_hash32(t->params, t->m, t->params.num_hashes);
+      g.H2 = secondary_hash(t);
+      g.threshold = t->params.iht_threshold;
+      reinterpret_cast<void (*)(SchemeArgs32)>(const_cast<void*>(ks.build))
+          <<<grid, kBlock, 0, st>>>(g);
+    }
     HIP_TRY(hipGetLastError());
     if (t->timing) HIP_TRY(hipEventRecord(t->ev[1], st));
     t->build_timed = t->timing;
@@ -229,25 +308,40 @@ bht_status find32_enqueue(const bht_table* t, const uint32_t* q, uint64_t n, uin
   if (!t->built) return fail(BHT_ERR_NOT_BUILT, "find before a successful build");
   if (n == 0) return BHT_OK;
   if (!q || !out_v || !out_f) return fail(BHT_ERR_INVALID_ARG, "null query or output pointer");
-  BuildKernel bk;
-  FindKernel fk;
-  if (!pick_cuckoo(t->b, t->tile, probes != nullptr, &bk, &fk, t->find_schedule))
+  KernelSet ks;
+  if (!pick(t, t->tile, t->find_schedule, probes != nullptr, &ks))
     return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
-  FindArgs32 g;
-  g.slots = t->d_slots;
-  g.queries = q;
-  g.n = n;
-  g.out_v = out_v;
-  g.out_f = out_f;
-  g.probes = probes;
-  g.H = make_hash32(t->params, t->m, t->params.num_hashes);
-  const uint32_t sched = t->find_schedule ? t->find_schedule : kDefaultSchedule;
-  const int grid = grid_for((const void*)fk, n, t->grid_blocks, sched == BHT_FIND_CHUNK ? 16 : 0);
+  hipStream_t st = as_stream(stream);
+  const int grid = grid_for(ks.find, n, t->grid_blocks, ks.chunk ? 16 : 0);
   bht_table* mt = const_cast<bht_table*>(t);
-  if (t->timing) HIP_TRY(hipEventRecord(t->ev[2], as_stream(stream)));
-  fk<<<grid, kBlock, 0, as_stream(stream)>>>(g);
+  if (t->timing) HIP_TRY(hipEventRecord(t->ev[2], st));
+  if (ks.kind == Kind::Cuckoo) {
+    FindArgs32 g;
+    g.slots = t->d_slots;
+    g.queries = q;
+    g.n = n;
+    g.out_v = out_v;
+    g.out_f = out_f;
+    g.probes = probes;
+    g.H = make_hash32(t->params, t->m, t->params.num_hashes);
+    reinterpret_cast<void (*)(FindArgs32)>(const_cast<void*>(ks.find)) <<<grid, kBlock, 0, st>>>(g);
+  } else {
+    SchemeFindArgs32 g;
+    g.slots = t->d_slots;
+    g.slots2 = secondary_slots(t);
+    g.queries = q;
+    g.n = n;
+    g.out_v = out_v;
+    g.out_f = out_f;
+    g.probes = probes;
+    g.H = make_hash32(t->params, t->m, t->params.num_hashes);
+    g.H2 = secondary_hash(t);
+    g.rounds = t->params.num_hashes;
+    reinterpret_cast<void (*)(SchemeFindArgs32)>(const_cast<void*>(ks.find))
+        <<<grid, kBlock, 0, st>>>(g);
+  }
   HIP_TRY(hipGetLastError());
-  if (t->timing) HIP_TRY(hipEventRecord(t->ev[3], as_stream(stream)));
+  if (t->timing) HIP_TRY(hipEventRecord(t->ev[3], st));
   mt->find_timed = t->timing;
   return BHT_OK;
 }
@@ -302,10 +396,12 @@ bht_status bht_create(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme 
   t->m = m;
   t->key_bits = params->key_bits;
   t->params = *params;
-  if (t->params.max_chain == 0 && scheme != BHT_BCHT && scheme != BHT_CHT1) t->params.max_chain = 0;
-  t->tile = default_tile(bucket_size);
+  t->tile = default_tile(scheme, bucket_size);
   const uint64_t slot_words = params->key_bits == 64 ? 2 : 1;
-  t->words = m * bucket_size * slot_words;
+  t->slots = m * bucket_size;
+  if (scheme == BHT_IHT && params->iht_secondary_b)
+    t->slots += params->iht_secondary_m * params->iht_secondary_b;
+  t->words = t->slots * slot_words;
   hipError_t e = hipGetDevice(&t->device);
   if (e == hipSuccess) e = hipMalloc(&t->d_slots, t->words * sizeof(uint64_t));
   if (e != hipSuccess) {
@@ -408,9 +504,8 @@ bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning) {
   if (!t || !tuning) return fail(BHT_ERR_INVALID_ARG, "null argument");
   const uint32_t w = tuning->tile_width ? tuning->tile_width : t->tile;
   if (tuning->find_schedule > BHT_FIND_CHUNK) return fail(BHT_ERR_INVALID_ARG, "bad schedule");
-  BuildKernel bk;
-  FindKernel fk;
-  if (!pick_cuckoo(t->b, w, false, &bk, &fk, tuning->find_schedule))
+  KernelSet ks;
+  if (!pick(t, w, tuning->find_schedule, false, &ks))
     return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
   t->tile = w;
   t->find_schedule = tuning->find_schedule;
@@ -474,7 +569,7 @@ bht_status bht_download(const bht_table* t, void* host_slots) {
 
 bht_status bht_upload(bht_table* t, const void* host_slots, uint64_t n_stored) {
   if (!t || !host_slots) return fail(BHT_ERR_INVALID_ARG, "null argument");
-  if (n_stored > t->m * (uint64_t)t->b) return fail(BHT_ERR_CAPACITY, "more pairs than slots");
+  if (n_stored > t->slots) return fail(BHT_ERR_CAPACITY, "more pairs than slots");
   HIP_TRY(hipDeviceSynchronize());
   HIP_TRY(hipMemcpy(t->d_slots, host_slots, t->words * sizeof(uint64_t), hipMemcpyHostToDevice));
   t->built = true;

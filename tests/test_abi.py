@@ -83,3 +83,24 @@ def test_product_path_never_imports_the_oracle():
                 for banned in ("import oracle", "from oracle", "liboracle", "oracle.h",
                                "import datagen", "from datagen"):
                     assert banned not in text, (fn, banned)
+
+
+def test_create_rejects_bad_parameters_before_touching_the_device():
+    import paper_2108_07232_amd as bht
+    a, c = datagen.hash_constants(1, 3)
+    cases = [
+        ("bcht", 16, dict(a=a, b=c, key_bits=16)),         # key width
+        ("bcht", 12, dict(a=a, b=c)),                       # bucket size
+        ("cht1", 4, dict(a=a, b=c)),                        # single-slot scheme
+        ("bp2ht", 16, dict(a=a, b=c)),                      # needs two hashes
+        ("iht", 8, dict(a=a, b=c)),                         # bucket size
+        ("iht", 16, dict(a=a, b=c, iht_threshold=17)),      # threshold above b
+        ("iht", 16, dict(a=a, b=c, iht_secondary_b=4, iht_secondary_m=10)),
+        ("bcht", 16, dict(a=[0, 1, 2], b=[0, 0, 0])),       # a must be >= 1
+        ("bcht", 16, dict(a=[4294967291, 1, 2], b=[0, 0, 0])),  # a must be < p
+    ]
+    for scheme, bsz, kw in cases:
+        p = bht.make_params(**kw)
+        with pytest.raises(bht.BhtError) as e:
+            bht.bht_create(1000, bsz, scheme, p)
+        assert e.value.status in (bht.BHT_ERR_INVALID_ARG, bht.BHT_ERR_UNSUPPORTED), (scheme, bsz, kw)

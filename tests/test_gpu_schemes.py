@@ -1,0 +1,158 @@
+"""GPU parity of the comparison schemes on the shared tile skeleton:
+bucketed power-of-two choices, iceberg (one level, and two levels with an
+8-slot secondary array of 1/8 the primary's slots), and the bucket-size-1
+cuckoo table with three and four hashes."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests._util import dev, host_u32, host_u8, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def bht():
+    import paper_2108_07232_amd
+    return paper_2108_07232_amd
+
+
+def iceberg_params(n, lf, seed, b=16, b2=0, threshold=None):
+    """Two-level geometry: secondary slots = primary slots / 8, load factor
+    over all slots; one level when b2 = 0."""
+    p = oracle.params_for("iht", n, lf, seed, b=b)
+    if b2:
+        cap = datagen.capacity_for(n, lf)
+        per_primary = b + b / 8.0      # slots per primary bucket incl. its secondary share
+        p.m = max(4, int(np.ceil(cap / per_primary)))
+        p.b2 = b2
+        p.m2 = max(1, p.m * b // 8 // b2)
+    p.threshold = b if threshold is None else threshold
+    return p
+
+
+def gpu_table(p, schedule=0):
+    return bht().Table(p.m * p.b, p.b, p.scheme, p.a, p.c, rng_seed=p.rng_seed,
+                       max_chain=p.max_chain, iht_threshold=p.threshold, iht_secondary_b=p.b2,
+                       iht_secondary_m=p.m2, find_schedule=schedule)
+
+
+def check_find(t, p, keys, vals, q):
+    import torch
+    import paper_2108_07232_amd as B
+    n = len(q)
+    out_v = torch.empty(n, dtype=torch.int32, device="cuda")
+    out_f = torch.empty(n, dtype=torch.uint8, device="cuda")
+    probes = torch.empty(n, dtype=torch.uint8, device="cuda")
+    B.bht_find_counted(t.handle, dev(q), out_v, out_f, probes)
+    torch.cuda.synchronize()
+    bv, bf = oracle.brute_find32(keys, vals, q)
+    np.testing.assert_array_equal(host_u8(out_f), bf)
+    np.testing.assert_array_equal(host_u32(out_v), bv)
+    # per-query probes equal the oracle's on the GPU's own layout
+    _, _, _, per = oracle.find32(p, t.download(), q)
+    np.testing.assert_array_equal(host_u8(probes), per)
+
+
+CASES = [
+    # scheme, b, b2, threshold, lf, n
+    ("bp2ht", 16, 0, 0, 0.8, 1 << 18),
+    ("bp2ht", 32, 0, 0, 0.88, 1 << 18),
+    ("bp2ht", 8, 0, 0, 0.6, 50000),
+    ("bp2ht", 16, 0, 0, 0.7, 999),
+    ("iht", 16, 0, 12, 0.8, 1 << 18),
+    ("iht", 16, 0, 12, 0.85, 30001),
+    ("iht", 32, 0, 25, 0.9, 1 << 18),
+    ("iht", 16, 8, 16, 0.8, 1 << 18),
+    ("iht", 16, 8, 16, 0.75, 4097),
+    ("iht", 32, 8, 32, 0.85, 1 << 17),
+    ("cht1", 1, 0, 0, 0.8, 1 << 18),
+]
+
+
+@pytest.mark.parametrize("scheme,b,b2,thr,lf,n", CASES)
+def test_scheme_build_find_parity(scheme, b, b2, thr, lf, n):
+    import torch
+    B = bht()
+    keys, vals = workload(n, 31)
+    for s in range(12):
+        if scheme == "iht":
+            p = iceberg_params(n, lf, 3100 + s, b=b, b2=b2, threshold=thr)
+        else:
+            p = oracle.params_for(scheme, n, lf, 3100 + s, b=b)
+        t = gpu_table(p)
+        total = torch.zeros(1, dtype=torch.int64, device="cuda")
+        st = B.bht_build_counted(t.handle, dev(keys), dev(vals), total)
+        if st == B.BHT_OK:
+            break
+        assert st == B.BHT_ERR_BUILD_FAILED
+        t.close()
+    assert st == B.BHT_OK
+    layout = t.download()
+    code, msg = oracle.check32(p, layout, keys, vals)
+    assert code == 0, msg
+    ins = int(total.item())
+    if scheme == "bp2ht":
+        assert ins == 2 * n                       # Section VII-A: always two buckets
+    elif scheme == "iht":
+        assert n <= ins <= 3 * n and (ins - n) % 2 == 0
+    for frac in (1.0, 0.5, 0.0):
+        check_find(t, p, keys, vals, datagen.mixed_queries(n, n, frac, 31))
+    t.close()
+
+
+@pytest.mark.parametrize("scheme,b,b2,thr", [("bp2ht", 16, 0, 0), ("iht", 16, 0, 12),
+                                             ("iht", 16, 8, 16), ("cht1", 1, 0, 0)])
+def test_scheme_find_on_oracle_layout(scheme, b, b2, thr):
+    n = 20000
+    keys, vals = workload(n, 41)
+    for s in range(20):
+        if scheme == "iht":
+            p = iceberg_params(n, 0.75, 4100 + s, b=b, b2=b2, threshold=thr)
+        else:
+            p = oracle.params_for(scheme, n, 0.75, 4100 + s, b=b)
+        st, layout, _ = oracle.build32(p, keys, vals)
+        if st == oracle.OK:
+            break
+    assert st == oracle.OK
+    t = gpu_table(p)
+    t.upload(layout, n)
+    check_find(t, p, keys, vals, datagen.mixed_queries(n, 2 * n, 0.5, 41))
+    t.close()
+
+
+def test_scheme_failures_are_reported():
+    B = bht()
+    n = 20000
+    keys, vals = workload(n, 5)
+    # power of two choices cannot reach LF 0.97 with 8-slot buckets
+    p = oracle.params_for("bp2ht", n, 0.97, 5, b=8)
+    t = gpu_table(p)
+    assert t.build(dev(keys), dev(vals)) == B.BHT_ERR_BUILD_FAILED
+    t.close()
+    # two-level iceberg at full load overflows its small secondary level
+    p = iceberg_params(n, 0.99, 5, b=16, b2=8, threshold=16)
+    t = gpu_table(p)
+    assert t.build(dev(keys), dev(vals)) == B.BHT_ERR_BUILD_FAILED
+    t.close()
+
+
+def test_power_of_two_places_in_less_loaded_bucket_when_uncontended():
+    # one wave's worth of keys on a large table: no two keys share a bucket,
+    # so every key lands in H0 exactly (both buckets empty, ties to H0)
+    n = 64
+    for seed in range(6, 100):
+        keys, vals = workload(n, seed)
+        p = oracle.params_for("bp2ht", n, 0.001, seed, b=16)
+        cands = np.concatenate([oracle.hash32_many(p.a[i], p.c[i], keys, p.m) for i in range(2)])
+        if len(np.unique(cands)) == 2 * n:     # no candidate bucket shared by two keys
+            break
+    t = gpu_table(p)
+    assert t.build(dev(keys), dev(vals)) == bht().BHT_OK
+    layout = t.download()
+    b0 = oracle.hash32_many(p.a[0], p.c[0], keys, p.m).astype(np.int64)
+    occ = np.nonzero((layout & np.uint64(0xFFFFFFFF)) != np.uint64(0xFFFFFFFF))[0]
+    stored_keys = (layout[occ] & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    where = dict(zip(stored_keys.tolist(), (occ // 16).tolist()))
+    assert all(where[int(k)] == int(b) for k, b in zip(keys, b0))
+    t.close()
