@@ -26,6 +26,9 @@ WRITE_GRANULE = 64             # bytes charged per slot atomic (one HBM3E burst)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="bcht", choices=["bcht", "schemes"],
+                    help="bcht: the headline BCHT workload; schemes: the comparison of "
+                         "BCHT, BP2HT, two-level iceberg, 1CHT and 64-bit BCHT")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--log2n", type=int, default=28)
@@ -155,12 +158,155 @@ def cpu_baseline(args, n_s):
     }, probes
 
 
+SCHEME_CONFIGS = [
+    # name, scheme, slots per bucket, hashes, load factor, secondary bucket slots, 64-bit
+    ("bcht", "bcht", 16, 3, 0.9, 0, False),
+    ("bp2ht", "bp2ht", 16, 2, 0.9, 0, False),
+    ("iht_two_level", "iht", 16, 3, 0.9, 8, False),
+    ("cht1", "cht1", 1, 3, 0.8, 0, False),
+    ("bcht64", "bcht", 8, 3, 0.9, 0, True),
+]
+
+
+def scheme_geometry(scheme, n, lf, b, b2):
+    """(primary buckets, secondary buckets).  The two-level iceberg table puts
+    1/8 of the primary's slots in 8-slot secondary buckets and the load factor
+    counts both levels."""
+    import datagen
+    cap = datagen.capacity_for(n, lf)
+    if scheme == "iht" and b2:
+        m = -(-cap * 8 // (9 * b))
+        return m, max(1, m * b // 8 // b2)
+    return -(-cap // b), 0
+
+
+def run_schemes(args):
+    """Comparison workload: each scheme built from 2^n pairs and queried with
+    2^n queries at 100/0/50% positive.  A scheme that cannot build at its
+    configured load factor is retried with new constants, then at lower
+    load factors (0.01 steps); the load factor reached is reported."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2108_07232_amd as bht
+
+    n = 1 << args.log2n
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    results = {}
+    for name, scheme, b, h, lf0, b2, wide in SCHEME_CONFIGS:
+        log("scheme %s: generating 2^%d inputs" % (name, args.log2n))
+        if wide:
+            keys, vals = datagen.unique_keys64(n, args.seed), datagen.values64(n, args.seed)
+            view = np.int64
+        else:
+            keys, vals = datagen.unique_keys(n, args.seed), datagen.values(n, args.seed)
+            view = np.int32
+        d_keys = torch.from_numpy(keys.view(view)).to(dev)
+        d_vals = torch.from_numpy(vals.view(view)).to(dev)
+        d_q = {}
+        for qname, frac in (("find_pos", 1.0), ("find_neg", 0.0), ("find_mix", 0.5)):
+            q = datagen.mixed_queries(n, n, frac, args.seed, wide=wide)
+            d_q[qname] = torch.from_numpy(q.view(view)).to(dev)
+        del keys, vals
+        out_v = torch.empty(n, dtype=torch.int64 if wide else torch.int32, device=dev)
+        out_f = torch.empty(n, dtype=torch.uint8, device=dev)
+        lf, table, failures, seed = lf0, None, 0, args.seed
+        while table is None and lf >= 0.5:
+            m, m2 = scheme_geometry(scheme, n, lf, b, b2)
+            for _ in range(3):
+                hc = datagen.hash_constants64 if wide else datagen.hash_constants
+                a, c = hc(seed, h)
+                t = bht.Table(m * b, b, scheme, a, c, key_bits=64 if wide else 32,
+                              rng_seed=datagen.rng_seed(seed), iht_threshold=b if b2 else 0,
+                              iht_secondary_b=b2, iht_secondary_m=m2)
+                st = t.build(d_keys, d_vals)
+                seed += 7919
+                if st == bht.BHT_OK:
+                    table = t
+                    table.m2 = m2
+                    break
+                failures += 1
+                t.close()
+            if table is None:
+                log("scheme %s: no build at LF %.2f" % (name, lf))
+                lf = round(lf - 0.01, 2)
+        if table is None:
+            results[name] = {"built": False}
+            continue
+        bht.bht_enable_timing(table.handle, True)
+        ms = {"build": [], "find_pos": [], "find_neg": [], "find_mix": []}
+        timed_failures = 0
+        for _ in range(args.steps):
+            # near a scheme's load limit a concurrent build can fail where an
+            # earlier one succeeded: retry with new constants, as Section VII does
+            while table.build(d_keys, d_vals) != bht.BHT_OK:
+                timed_failures += 1
+                if timed_failures > 50:
+                    raise RuntimeError("scheme %s keeps failing at LF %.2f" % (name, lf))
+                hc = datagen.hash_constants64 if wide else datagen.hash_constants
+                a, c = hc(seed, h)
+                seed += 7919
+                bht.bht_reseed(table.handle, bht.make_params(
+                    a, c, key_bits=64 if wide else 32, rng_seed=datagen.rng_seed(seed),
+                    iht_threshold=b if b2 else 0, iht_secondary_b=b2, iht_secondary_m=table.m2))
+            ms["build"].append(bht.bht_kernel_ms(table.handle)[0])
+            for qname in ("find_pos", "find_neg", "find_mix"):
+                if wide:
+                    bht.bht_find64(table.handle, d_q[qname], out_v, out_f, stream=stream)
+                else:
+                    bht.bht_find(table.handle, d_q[qname], out_v, out_f, stream=stream)
+                ms[qname].append(bht.bht_kernel_ms(table.handle)[1])
+        entry = {"load_factor": lf, "configured_load_factor": lf0,
+                 "build_failures": failures + timed_failures,
+                 "buckets": table.info[0], "bucket_slots": b, "secondary_bucket_slots": b2,
+                 "hashes": h, "key_bits": 64 if wide else 32}
+        if not wide:
+            # probe averages from the instrumented kernels (untimed runs)
+            total = torch.zeros(1, dtype=torch.int64, device=dev)
+            bht.bht_build_counted(table.handle, d_keys, d_vals, total)
+            probes = {"insert": int(total.item()) / n}
+            pr = torch.empty(n, dtype=torch.uint8, device=dev)
+            for qname in ("find_pos", "find_neg", "find_mix"):
+                bht.bht_find_counted(table.handle, d_q[qname], out_v, out_f, pr, stream=stream)
+                probes[qname.replace("find_", "")] = float(pr.sum(dtype=torch.int64).item()) / n
+            entry["probes_per_key"] = {k: round(v, 4) for k, v in probes.items()}
+            entry["accesses_gps"] = {}
+        for k, v in ms.items():
+            avg = float(np.mean(v))
+            entry[k + "_ms"] = round(avg, 4)
+            entry[k + "_gkeys_s"] = round(n / (avg * 1e-3) / 1e9, 4)
+            if not wide:
+                p = entry["probes_per_key"]["insert" if k == "build" else k.replace("find_", "")]
+                entry["accesses_gps"][k] = round(p * n / (avg * 1e-3) / 1e9, 2)
+        results[name] = entry
+        log("scheme %s: %s" % (name, json.dumps(entry)))
+        table.close()
+        del d_keys, d_vals, d_q, out_v, out_f
+        torch.cuda.empty_cache()
+    line = json.dumps({"workload": "schemes", "n_keys": n, "results": results,
+                       "note": "accesses_gps = bucket reads per second; random accesses of "
+                               "32-128 B run at about 53 G/s on this part"})
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "a") as f:
+            f.write(line + "\n")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "schemes":
+        import torch
+        torch.cuda.set_device(0)
+        if args.log2n == 28:
+            args.log2n = 27
+        run_schemes(args)
+        return
 
     import numpy as np
     import torch

@@ -98,14 +98,17 @@ uint64_t dg_feistel64(uint64_t x, uint64_t k0, uint64_t k1, uint64_t k2, uint64_
   return feistel_bits(x, rk, 32);
 }
 
-/* Distinct uint64 keys, never all ones. */
+/* Distinct uint64 keys below 2^64 - 2 (the two largest values are reserved
+ * markers of 64-bit tables): images cycle-walked out of the reserved pair. */
+static inline uint64_t key64(uint64_t j, const uint64_t rk[4]) {
+  uint64_t y = feistel_bits(j, rk, 32);
+  while (y >= 0xFFFFFFFFFFFFFFFEULL) y = feistel_bits(y, rk, 32);
+  return y;
+}
+
 void dg_keys64(const uint64_t rk[4], uint64_t start, uint64_t count, uint64_t* out) {
-  const uint64_t walk = feistel_bits(~0ULL, rk, 32);
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < (int64_t)count; i++) {
-    uint64_t y = feistel_bits(start + (uint64_t)i, rk, 32);
-    out[i] = (y == ~0ULL) ? walk : y;
-  }
+  for (int64_t i = 0; i < (int64_t)count; i++) out[i] = key64(start + (uint64_t)i, rk);
 }
 
 static int half_bits(uint64_t n) {
@@ -147,13 +150,11 @@ void dg_queries32(const uint32_t rk_keys[4], const uint64_t rk_pos[4], uint64_t 
 void dg_queries64(const uint64_t rk_keys[4], const uint64_t rk_pos[4], uint64_t n,
                   const uint64_t rk_mix[4], uint64_t count, uint64_t npos, int shuffle,
                   uint64_t* out) {
-  const uint64_t walk = feistel_bits(~0ULL, rk_keys, 32);
   const int hn = half_bits(n ? n : 1), hc = half_bits(count ? count : 1);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < (int64_t)count; i++) {
     uint64_t j = shuffle ? perm_at((uint64_t)i, count, rk_mix, hc) : (uint64_t)i;
     uint64_t idx = (j < npos) ? perm_at(j % n, n, rk_pos, hn) : n + (j - npos);
-    uint64_t y = feistel_bits(idx, rk_keys, 32);
-    out[i] = (y == ~0ULL) ? walk : y;
+    out[i] = key64(idx, rk_keys);
   }
 }

@@ -13,6 +13,7 @@
 #include "bht_diag.hpp"
 #include "bht_kernels.hpp"
 #include "bht_schemes.hpp"
+#include "bht_wide.hpp"
 
 using namespace bht;
 
@@ -92,6 +93,18 @@ int grid_for(const void* kernel, uint64_t items, uint32_t fixed = 0, uint64_t it
     grid = std::max<uint64_t>(grid, std::min<uint64_t>(
         (items + kBlock * items_per_lane - 1) / (kBlock * items_per_lane), 1u << 20));
   return (int)std::max<uint64_t>(1, grid);
+}
+
+Hash64 make_hash64(const bht_params& p, uint64_t m, uint32_t h) {
+  Hash64 H;
+  for (int i = 0; i < 4; ++i) {
+    H.a[i] = p.a[i];
+    H.c[i] = p.b[i];
+  }
+  H.m = m;
+  H.M = UINT64_MAX / m;
+  H.h = h;
+  return H;
 }
 
 Hash32 make_hash32(const bht_params& p, uint64_t m, uint32_t h) {
@@ -490,20 +503,72 @@ bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint6
 
 bht_status bht_build64(bht_table* t, const uint64_t* d_keys, const uint64_t* d_values,
                        uint64_t n, void* stream) {
-  (void)t; (void)d_keys; (void)d_values; (void)n; (void)stream;
-  return fail(BHT_ERR_UNSUPPORTED, "64-bit keys not available in this build");
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  if (t->key_bits != 64) return fail(BHT_ERR_INVALID_ARG, "table holds 32-bit keys");
+  if (n > t->slots) return fail(BHT_ERR_CAPACITY, "more pairs than slots");
+  if (n && (!d_keys || !d_values)) return fail(BHT_ERR_INVALID_ARG, "null key or value pointer");
+  if (t->b != 8) return fail(BHT_ERR_UNSUPPORTED, "64-bit tables use 8-slot buckets");
+  hipStream_t st = as_stream(stream);
+  t->built = false;
+  bht_status s = launch_fill(t, st);
+  if (s != BHT_OK) return s;
+  if (n) {
+    WideBuildArgs g;
+    g.slots = t->d_slots;
+    g.keys = d_keys;
+    g.vals = d_values;
+    g.n = n;
+    g.status = t->d_status;
+    g.H = make_hash64(t->params, t->m, t->params.num_hashes);
+    g.max_chain = t->params.max_chain;
+    g.rng_seed = t->params.rng_seed;
+    const int grid = grid_for((const void*)wide_build_kernel<8>, n, t->grid_blocks);
+    if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
+    wide_build_kernel<8><<<grid, kBlock, 0, st>>>(g);
+    HIP_TRY(hipGetLastError());
+    if (t->timing) HIP_TRY(hipEventRecord(t->ev[1], st));
+    t->build_timed = t->timing;
+  }
+  t->pending = true;
+  t->pending_n = n;
+  return bht_build_wait(t, stream);
 }
 
 bht_status bht_find64(const bht_table* t, const uint64_t* d_queries, uint64_t n,
                       uint64_t* d_out_values, uint8_t* d_out_found, void* stream) {
-  (void)t; (void)d_queries; (void)n; (void)d_out_values; (void)d_out_found; (void)stream;
-  return fail(BHT_ERR_UNSUPPORTED, "64-bit keys not available in this build");
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  if (t->key_bits != 64) return fail(BHT_ERR_INVALID_ARG, "table holds 32-bit keys");
+  if (!t->built) return fail(BHT_ERR_NOT_BUILT, "find before a successful build");
+  if (n == 0) return BHT_OK;
+  if (!d_queries || !d_out_values || !d_out_found)
+    return fail(BHT_ERR_INVALID_ARG, "null query or output pointer");
+  WideFindArgs g;
+  g.slots = t->d_slots;
+  g.queries = d_queries;
+  g.n = n;
+  g.out_v = d_out_values;
+  g.out_f = d_out_found;
+  g.H = make_hash64(t->params, t->m, t->params.num_hashes);
+  hipStream_t st = as_stream(stream);
+  const int grid = grid_for((const void*)wide_find_chunk_kernel<8>, n, t->grid_blocks, 16);
+  bht_table* mt = const_cast<bht_table*>(t);
+  if (t->timing) HIP_TRY(hipEventRecord(t->ev[2], st));
+  wide_find_chunk_kernel<8><<<grid, kBlock, 0, st>>>(g);
+  HIP_TRY(hipGetLastError());
+  if (t->timing) HIP_TRY(hipEventRecord(t->ev[3], st));
+  mt->find_timed = t->timing;
+  return BHT_OK;
 }
 
 bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning) {
   if (!t || !tuning) return fail(BHT_ERR_INVALID_ARG, "null argument");
   const uint32_t w = tuning->tile_width ? tuning->tile_width : t->tile;
   if (tuning->find_schedule > BHT_FIND_CHUNK) return fail(BHT_ERR_INVALID_ARG, "bad schedule");
+  if (t->key_bits == 64) {
+    if (w != 8) return fail(BHT_ERR_UNSUPPORTED, "64-bit tables read buckets with 8 lanes");
+    t->grid_blocks = tuning->grid_blocks;
+    return BHT_OK;
+  }
   KernelSet ks;
   if (!pick(t, w, tuning->find_schedule, false, &ks))
     return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
