@@ -26,7 +26,13 @@ WRITE_GRANULE = 64             # bytes charged per slot atomic (one HBM3E burst)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="bcht", choices=["bcht", "schemes"],
+    ap.add_argument("--tables", type=int, default=4096, help="batched workload: table count")
+    ap.add_argument("--requests", type=int, default=4000, help="serve workload: requests per rate")
+    ap.add_argument("--rates", default="2000,10000,50000",
+                    help="serve workload: arrival rates (requests/s), comma separated")
+    ap.add_argument("--initial-tables", type=int, default=512)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--workload", default="bcht", choices=["bcht", "schemes", "batched", "serve"],
                     help="bcht: the headline BCHT workload; schemes: the comparison of "
                          "BCHT, BP2HT, two-level iceberg, 1CHT and 64-bit BCHT")
     ap.add_argument("--steps", type=int, default=5)
@@ -294,12 +300,264 @@ def run_schemes(args):
             f.write(line + "\n")
 
 
+def run_batched(args):
+    """Batched workload: `tables` BCHT tables with key counts log-uniform in
+    [2^10, 2^22] at LF 0.9, each followed by as many queries, 50% positive.
+    The autotuner picks bucket size, tile width and item size on a sample of
+    the tables; the full batch then runs as one graph (reset, persistent
+    build, persistent query) and is compared with plain per-table calls."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2108_07232_amd as bht
+    from paper_2108_07232_amd import autotune
+
+    dev = torch.device("cuda", 0)
+    count = args.tables
+    sizes = datagen.log_uniform_sizes(count, 10, 22, args.seed).astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    total = int(offs[-1])
+    log("batched: %d tables, %d keys, %d queries; generating" % (count, total, total))
+    t0 = time.time()
+    keys = np.empty(total, np.uint32)
+    vals = np.empty(total, np.uint32)
+    qs = np.empty(total, np.uint32)
+    for i, n in enumerate(sizes.tolist()):
+        s = args.seed * 1000003 + i
+        keys[offs[i]:offs[i + 1]] = datagen.unique_keys(n, s)
+        vals[offs[i]:offs[i + 1]] = datagen.values(n, s)
+        qs[offs[i]:offs[i + 1]] = datagen.mixed_queries(n, n, 0.5, s)
+    d_keys = torch.from_numpy(keys.view(np.int32)).to(dev)
+    d_vals = torch.from_numpy(vals.view(np.int32)).to(dev)
+    d_q = torch.from_numpy(qs.view(np.int32)).to(dev)
+    del keys, vals, qs
+    out_v = torch.empty(total, dtype=torch.int32, device=dev)
+    out_f = torch.empty(total, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    log("inputs resident (%.1f s)" % (time.time() - t0))
+    specs = []
+    for i, n in enumerate(sizes.tolist()):
+        s = args.seed * 1000003 + i
+        a, c = datagen.hash_constants(s, 3)
+        sl = slice(int(offs[i]), int(offs[i + 1]))
+        specs.append(dict(capacity=datagen.capacity_for(n, 0.9), a=a, c=c,
+                          rng_seed=datagen.rng_seed(s), keys=d_keys[sl], vals=d_vals[sl],
+                          queries=d_q[sl], out_v=out_v[sl], out_f=out_f[sl]))
+    sample = specs[::8]
+    best, table = autotune.tune(bht, torch, sample, reps=3, log=log)
+    b, w, item = best
+    log("autotuner choice: bucket %d, tile %d, item %d" % best)
+    sec, sts = autotune.time_batch(bht, torch, specs, b, w, item, reps=args.steps)
+    failed = sum(1 for s in sts if s != bht.BHT_OK)
+    found = int(out_f.sum(dtype=torch.int64).item())
+    # plain per-table calls with the same configuration
+    tables = [bht.Table(s["capacity"], b, "bcht", s["a"], s["c"], rng_seed=s["rng_seed"], tile=w)
+              for s in specs]
+    stream = torch.cuda.current_stream()
+
+    def plain():
+        for t, s in zip(tables, specs):
+            st = bht.bht_build(t.handle, s["keys"], s["vals"], stream=stream)
+            if st == bht.BHT_OK:
+                bht.bht_find(t.handle, s["queries"], s["out_v"], s["out_f"], stream=stream)
+        torch.cuda.synchronize()
+
+    plain()
+    times = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain()
+        times.append(time.perf_counter() - t0)
+    times.sort()
+    plain_sec = times[len(times) // 2]
+    for t in tables:
+        t.close()
+    ops = 2 * total
+    line = json.dumps({
+        "workload": "batched", "tables": count, "keys": total, "queries": total,
+        "key_range_log2": [10, 22], "load_factor": 0.9, "positive_fraction": 0.5,
+        "autotune": {"choice": {"bucket": b, "tile": w, "item": item},
+                     "sample_tables": len(sample),
+                     "ms": {"b%d_w%d_i%d" % k: round(v * 1e3, 3) for k, v in table.items()}},
+        "batched": {"seconds": round(sec, 5), "gops_s": round(ops / sec / 1e9, 3),
+                    "failed_tables": failed, "found": found},
+        "plain_per_table": {"seconds": round(plain_sec, 5), "gops_s": round(ops / plain_sec / 1e9, 3)},
+        "speedup": round(plain_sec / sec, 3),
+        "unit": "G keys+queries per second",
+    })
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "a") as f:
+            f.write(line + "\n")
+
+
+def make_serve_requests(torch, n_initial, initial_sizes, count, rate, seed, build_fraction=0.05,
+                        lookup_log2=(8, 20), table_log2=(12, 24), positive=0.7):
+    """Open-loop request stream: Poisson arrivals at `rate`; a request is a
+    build of a new table (size log-uniform in 2^table_log2) with probability
+    build_fraction, else a lookup batch (size log-uniform in 2^lookup_log2,
+    `positive` of it present) against a uniformly chosen table among the
+    initial ones and those whose builds were requested earlier."""
+    import numpy as np
+
+    import datagen
+    from paper_2108_07232_amd.serve import Request
+    dev = torch.device("cuda", 0)
+    u = datagen.uniform01(3 * count, seed, datagen.TAG_ARRIVALS).reshape(count, 3)
+    gaps = -np.log1p(-u[:, 0]) / rate
+    arrivals = np.cumsum(gaps) - gaps[0]
+    sizes_b = datagen.log_uniform_sizes(count, table_log2[0], table_log2[1], seed, datagen.TAG_SIZES)
+    sizes_l = datagen.log_uniform_sizes(count, lookup_log2[0], lookup_log2[1], seed,
+                                        datagen.TAG_SIZES + 16)
+    table_sizes = list(initial_sizes)
+    reqs = []
+    for i in range(count):
+        s = seed * 7919 + i
+        if u[i, 1] < build_fraction:
+            n = int(sizes_b[i])
+            tid = len(table_sizes)
+            ts = table_seed(seed, tid)
+            a, c = datagen.hash_constants(ts, 3)
+            keys = torch.from_numpy(datagen.unique_keys(n, ts).view(np.int32)).to(dev)
+            vals = torch.from_numpy(datagen.values(n, ts).view(np.int32)).to(dev)
+            reqs.append(Request("build", float(arrivals[i]), tid, keys=keys, vals=vals,
+                                capacity=datagen.capacity_for(n, 0.9), a=tuple(a), c=tuple(c),
+                                rng_seed=datagen.rng_seed(ts)))
+            table_sizes.append(n)
+        else:
+            tid = min(int(u[i, 2] * len(table_sizes)), len(table_sizes) - 1)
+            n_q = int(sizes_l[i])
+            q = datagen.mixed_queries(table_sizes[tid], n_q, positive, table_seed(seed, tid),
+                                      shuffle_seed=s)
+            qd = torch.from_numpy(q.view(np.int32)).to(dev)
+            reqs.append(Request("lookup", float(arrivals[i]), tid, queries=qd,
+                                out_v=torch.empty(n_q, dtype=torch.int32, device=dev),
+                                out_f=torch.empty(n_q, dtype=torch.uint8, device=dev)))
+    return reqs
+
+
+def table_seed(seed, tid):
+    return seed * 1000003 + 17 * tid + 5
+
+
+def build_initial_tables(torch, bht, count, seed, log2_range=(12, 24)):
+    """The resident set: `count` tables, sizes log-uniform in 2^log2_range,
+    built with one batched pass.  Returns (tables, sizes)."""
+    import numpy as np
+
+    import datagen
+    dev = torch.device("cuda", 0)
+    sizes = datagen.log_uniform_sizes(count, log2_range[0], log2_range[1], seed).tolist()
+    tables, entries, keep = [], [], []
+    for tid, n in enumerate(sizes):
+        ts = table_seed(seed, tid)
+        a, c = datagen.hash_constants(ts, 3)
+        t = bht.Table(datagen.capacity_for(n, 0.9), 16, "bcht", a, c, rng_seed=datagen.rng_seed(ts))
+        k = torch.from_numpy(datagen.unique_keys(n, ts).view(np.int32)).to(dev)
+        v = torch.from_numpy(datagen.values(n, ts).view(np.int32)).to(dev)
+        keep.append((k, v))
+        tables.append(t)
+        entries.append((t.handle, k, v, None, None, None))
+    batch = bht.bht_batch_create(entries)
+    bht.bht_batch_run(batch)
+    rc, sts = bht.bht_batch_wait(batch, count)
+    bht.bht_batch_destroy(batch)
+    for tid, st in enumerate(sts):
+        retry = 0
+        while st != bht.BHT_OK:
+            retry += 1
+            a, c = datagen.hash_constants(table_seed(seed, tid) + 7919 * retry, 3)
+            bht.bht_reseed(tables[tid].handle, bht.make_params(a, c))
+            st = tables[tid].build(*keep[tid])
+    del keep
+    torch.cuda.synchronize()
+    return tables, sizes
+
+
+def run_serve(args):
+    """Serving workload: resident tables under an HBM budget, a Poisson
+    request stream (5% builds, 95% lookups) at each rate, served by the
+    continuous-batching loop and, as the baseline, one request at a time."""
+    import torch
+
+    import paper_2108_07232_amd as bht
+    from paper_2108_07232_amd import serve
+
+    rates = [float(x) for x in args.rates.split(",")]
+    log("serve: building %d resident tables" % args.initial_tables)
+    t0 = time.time()
+    tables, sizes = build_initial_tables(torch, bht, args.initial_tables, args.seed)
+    resident_bytes = sum(t.info[3] for t in tables)
+    log("resident set ready: %.2f GB, %d keys (%.1f s)" % (resident_bytes / 1e9, sum(sizes),
+                                                           time.time() - t0))
+    out = {"workload": "serve", "initial_tables": args.initial_tables, "initial_keys": int(sum(sizes)),
+           "resident_gb": round(resident_bytes / 1e9, 3), "budget_gb": args.budget_gb,
+           "requests_per_rate": args.requests, "rates": {}}
+    for rate in rates:
+        reqs = make_serve_requests(torch, args.initial_tables, sizes, args.requests, rate,
+                                   args.seed + int(rate))
+        work = sum((r.queries.numel() if r.kind == "lookup" else r.keys.numel()) for r in reqs)
+        entry = {}
+        for mode in ("continuous", "serial"):
+            for r in reqs:
+                r.done, r.status, r.launch = -1.0, -1, -1
+            if mode == "continuous":
+                srv = serve.Server(torch, int(args.budget_gb * 1e9))
+                for tid, t in enumerate(tables):
+                    srv.add_table(tid, t)
+                srv.run(reqs)
+                launches, evicted = srv.launches, srv.evicted
+                extra = [tid for tid in srv.tables if tid >= args.initial_tables]
+                for tid in extra:
+                    srv.tables.pop(tid).close()
+                for s in srv.lookup_slots:
+                    bht.bht_find_ctx_destroy(s.ctx)
+            else:
+                tabs = dict(enumerate(tables))
+                serve.serve_serial(torch, tabs, reqs)
+                launches, evicted = len(reqs), 0
+                for tid in [k for k in tabs if k >= args.initial_tables]:
+                    tabs.pop(tid).close()
+            span = max(r.done for r in reqs) - reqs[0].arrival
+            st = serve.latency_stats(reqs)
+            st.update({"requests_per_s": round(len(reqs) / span, 1),
+                       "gkeys_s": round(work / span / 1e9, 4), "launches": launches,
+                       "evicted_tables": evicted,
+                       "failed": sum(1 for r in reqs if r.status != bht.BHT_OK)})
+            entry[mode] = st
+            log("rate %g %s: %s" % (rate, mode, json.dumps(st)))
+        entry["throughput_ratio"] = round(entry["continuous"]["requests_per_s"] /
+                                          entry["serial"]["requests_per_s"], 3)
+        out["rates"][str(int(rate))] = entry
+        del reqs
+        torch.cuda.empty_cache()
+    for t in tables:
+        t.close()
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "a") as f:
+            f.write(line + "\n")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        import torch
+        torch.cuda.set_device(0)
+        run_serve(args)
+        return
+    if args.workload == "batched":
+        import torch
+        torch.cuda.set_device(0)
+        run_batched(args)
+        return
     if args.workload == "schemes":
         import torch
         torch.cuda.set_device(0)

@@ -166,12 +166,14 @@ def permutation(n: int, seed: int, tag: int = TAG_PERM) -> np.ndarray:
     return out
 
 
-def _queries(n: int, count: int, npos: int, seed: int, shuffle: bool, wide: bool):
+def _queries(n: int, count: int, npos: int, seed: int, shuffle: bool, wide: bool,
+             shuffle_seed=None):
     rk_keys = _round_keys(seed, TAG_KEYS)
     if not wide:
         rk_keys = (rk_keys & np.uint64(0xFFFFFFFF)).astype(np.uint32)
-    rk_pos = _round_keys(seed, TAG_PERM)
-    rk_mix = _round_keys(seed, TAG_MIX)
+    ss = seed if shuffle_seed is None else shuffle_seed
+    rk_pos = _round_keys(ss, TAG_PERM)
+    rk_mix = _round_keys(ss, TAG_MIX)
     out = np.empty(count, dtype=np.uint64 if wide else np.uint32)
     if count:
         fn = _native().dg_queries64 if wide else _native().dg_queries32
@@ -185,18 +187,19 @@ def positive_queries(n: int, seed: int, wide: bool = False) -> np.ndarray:
 
 
 def mixed_queries(n: int, count: int, positive_fraction: float, seed: int,
-                  wide: bool = False) -> np.ndarray:
+                  wide: bool = False, shuffle_seed=None) -> np.ndarray:
     """count queries against the first n keys of the seed's key stream.
 
     floor(fraction * count) of them are inserted keys (a prefix of the
     positive shuffle, repeated if it exceeds n); the rest are the keys that
     follow the n inserted ones in the stream, hence absent.  The union is
-    shuffled.
+    shuffled.  shuffle_seed (default: seed) selects which positives and
+    negatives are drawn and their order, over the same key stream.
     """
     npos = int(math.floor(positive_fraction * count))
     if npos > 0 and n == 0:
         raise ValueError("positive queries requested from an empty key set")
-    return _queries(n, count, npos, seed, True, wide)
+    return _queries(n, count, npos, seed, True, wide, shuffle_seed)
 
 
 def hash_constants(seed: int, h: int):

@@ -194,6 +194,60 @@ bht_status bht_diag_gather(const void* d_buf, uint64_t bytes, uint64_t n_reads, 
 bht_status bht_diag_cas(void* d_buf, uint64_t bytes, uint64_t n_ops, uint64_t seed,
                         uint64_t* d_sink, void* stream);
 
+/* Batched mode (not in the paper): many bucketed cuckoo tables of uneven
+ * sizes built and then queried together.  Every table of a batch is a
+ * 32-bit BHT_BCHT table with the same bucket size and tile width.  Entry i
+ * names its table, its n_keys input pairs and its n_queries queries with
+ * their output arrays (all caller-owned device memory, as for bht_build and
+ * bht_find).  bht_batch_create copies the table descriptors and the work
+ * items (ranges of item_size pairs or queries; 0 = 8192) to the device.
+ * bht_batch_run enqueues: a reset of all tables, one persistent build kernel
+ * and one persistent query kernel, both pulling (table, range) items from
+ * device-side queues; on a non-null stream the sequence is captured once
+ * into a HIP graph and replayed by later runs on that stream.
+ * bht_batch_wait waits for the stream and writes each table's build status
+ * to status_out[i] (may be NULL); it returns BHT_OK when every table built.
+ * A table whose build failed holds unspecified contents and unspecified
+ * query outputs: reseed it and run it again (alone or in a new batch). */
+typedef struct bht_batch bht_batch;
+typedef struct {
+  bht_table* table;
+  const uint32_t* d_keys;
+  const uint32_t* d_values;
+  uint64_t n_keys;
+  const uint32_t* d_queries;
+  uint64_t n_queries;
+  uint32_t* d_out_values;
+  uint8_t* d_out_found;
+} bht_batch_entry;
+bht_status bht_batch_create(const bht_batch_entry* entries, uint32_t count, uint32_t item_size,
+                            bht_batch** out);
+bht_status bht_batch_run(bht_batch* b, void* stream);
+bht_status bht_batch_wait(bht_batch* b, void* stream, bht_status* status_out);
+void bht_batch_destroy(bht_batch* b);
+
+/* Coalesced lookups (serving): one launch answers many query batches on
+ * many built 32-bit BCHT tables that share bucket size and tile width.  A
+ * context holds device and pinned host space for up to max_requests
+ * requests and max_items work items (one item = item_size queries of one
+ * request; 0 = 8192).  bht_multi_find stages the request descriptors,
+ * copies them asynchronously and launches one persistent query kernel on
+ * stream; outputs are as for bht_find.  A call first waits until the
+ * context's previous copies have completed, so one context serves one
+ * stream at a time (use one context per stream for overlap). */
+typedef struct bht_find_ctx bht_find_ctx;
+typedef struct {
+  const bht_table* table;
+  const uint32_t* d_queries;
+  uint64_t n;
+  uint32_t* d_out_values;
+  uint8_t* d_out_found;
+} bht_find_request;
+bht_status bht_find_ctx_create(uint32_t max_requests, uint64_t max_items, bht_find_ctx** out);
+bht_status bht_multi_find(bht_find_ctx* ctx, const bht_find_request* reqs, uint32_t count,
+                          uint32_t item_size, void* stream);
+void bht_find_ctx_destroy(bht_find_ctx* ctx);
+
 /* Host copy of the library's hash, for checking its arithmetic without a
  * GPU: ((a*k + b) mod p) mod m with the 32-bit family, and with the 64-bit
  * family. */

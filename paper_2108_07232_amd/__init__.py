@@ -50,6 +50,18 @@ class bht_tuning(ctypes.Structure):
                 ("grid_blocks", ctypes.c_uint32)]
 
 
+class bht_batch_entry(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_void_p), ("d_keys", ctypes.c_void_p),
+                ("d_values", ctypes.c_void_p), ("n_keys", ctypes.c_uint64),
+                ("d_queries", ctypes.c_void_p), ("n_queries", ctypes.c_uint64),
+                ("d_out_values", ctypes.c_void_p), ("d_out_found", ctypes.c_void_p)]
+
+
+class bht_find_request(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_void_p), ("d_queries", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("d_out_values", ctypes.c_void_p), ("d_out_found", ctypes.c_void_p)]
+
+
 BHT_FIND_DEFAULT, BHT_FIND_REFILL, BHT_FIND_CHUNK = 0, 1, 2
 FIND_SCHEDULES = {"default": 0, "refill": 1, "chunk": 2}
 
@@ -86,6 +98,13 @@ _SIGS = {
     "bht_diag_cas": (_st, [_p, _u64, _u64, _u64, _p, _p]),
     "bht_hash32": (_u64, [_u64, _u64, _u32, _u64]),
     "bht_hash64": (_u64, [_u64, _u64, _u64, _u64]),
+    "bht_batch_create": (_st, [ctypes.POINTER(bht_batch_entry), _u32, _u32, _pp]),
+    "bht_batch_run": (_st, [_p, _p]),
+    "bht_batch_wait": (_st, [_p, _p, ctypes.POINTER(ctypes.c_int)]),
+    "bht_batch_destroy": (None, [_p]),
+    "bht_find_ctx_create": (_st, [_u32, _u64, _pp]),
+    "bht_multi_find": (_st, [_p, ctypes.POINTER(bht_find_request), _u32, _u32, _p]),
+    "bht_find_ctx_destroy": (None, [_p]),
     "bht_status_string": (ctypes.c_char_p, [_st]),
     "bht_last_error": (ctypes.c_char_p, []),
 }
@@ -293,6 +312,72 @@ def bht_hash32(a: int, b: int, k: int, m: int) -> int:
 
 def bht_hash64(a: int, b: int, k: int, m: int) -> int:
     return int(_lib.bht_hash64(a, b, k, m))
+
+
+def _ptr_of(t):
+    if t is None:
+        return None
+    return t.data_ptr() if hasattr(t, "data_ptr") else int(t)
+
+
+def bht_batch_create(entries, item_size: int = 0):
+    """entries: sequence of (table handle, keys, values, queries, out_values,
+    out_found) with device tensors (queries/outputs may be None)."""
+    arr = (bht_batch_entry * len(entries))()
+    for i, (table, keys, vals, queries, out_v, out_f) in enumerate(entries):
+        arr[i].table = table.value if isinstance(table, ctypes.c_void_p) else table
+        arr[i].d_keys = _ptr_of(keys)
+        arr[i].d_values = _ptr_of(vals)
+        arr[i].n_keys = 0 if keys is None else keys.numel()
+        arr[i].d_queries = _ptr_of(queries)
+        arr[i].n_queries = 0 if queries is None else queries.numel()
+        arr[i].d_out_values = _ptr_of(out_v)
+        arr[i].d_out_found = _ptr_of(out_f)
+    out = ctypes.c_void_p()
+    _check(_lib.bht_batch_create(arr, len(entries), item_size, ctypes.byref(out)),
+           "bht_batch_create")
+    return out
+
+
+def bht_batch_run(batch, stream=None):
+    _check(_lib.bht_batch_run(batch, _stream(stream)), "bht_batch_run")
+
+
+def bht_batch_wait(batch, count: int, stream=None):
+    """Returns (overall status, list of per-table statuses)."""
+    st = (ctypes.c_int * count)()
+    rc = _lib.bht_batch_wait(batch, _stream(stream), st)
+    if rc not in (BHT_OK, BHT_ERR_BUILD_FAILED, BHT_ERR_SENTINEL_KEY):
+        _check(rc, "bht_batch_wait")
+    return rc, list(st)
+
+
+def bht_batch_destroy(batch):
+    _lib.bht_batch_destroy(batch)
+
+
+def bht_find_ctx_create(max_requests: int, max_items: int):
+    out = ctypes.c_void_p()
+    _check(_lib.bht_find_ctx_create(max_requests, max_items, ctypes.byref(out)),
+           "bht_find_ctx_create")
+    return out
+
+
+def bht_multi_find(ctx, requests, item_size: int = 0, stream=None):
+    """requests: sequence of (table handle, queries, out_values, out_found)."""
+    arr = (bht_find_request * len(requests))()
+    for i, (table, q, ov, of) in enumerate(requests):
+        arr[i].table = table.value if isinstance(table, ctypes.c_void_p) else table
+        arr[i].d_queries = _ptr_of(q)
+        arr[i].n = q.numel()
+        arr[i].d_out_values = _ptr_of(ov)
+        arr[i].d_out_found = _ptr_of(of)
+    _check(_lib.bht_multi_find(ctx, arr, len(requests), item_size, _stream(stream)),
+           "bht_multi_find")
+
+
+def bht_find_ctx_destroy(ctx):
+    _lib.bht_find_ctx_destroy(ctx)
 
 
 def bht_status_string(status: int) -> str:

@@ -8,12 +8,15 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <unordered_set>
+#include <vector>
 
 #include "bht.h"
 #include "bht_diag.hpp"
 #include "bht_kernels.hpp"
 #include "bht_schemes.hpp"
 #include "bht_wide.hpp"
+#include "bht_batch.hpp"
 
 using namespace bht;
 
@@ -39,6 +42,36 @@ struct bht_table {
   bool timing;             // record events around the main kernels
   hipEvent_t ev[4];        // build start/stop, find start/stop
   bool build_timed, find_timed;
+};
+
+struct bht_batch {
+  uint32_t count;
+  std::vector<bht_table*> tables;
+  std::vector<uint64_t> n_keys;
+  uint32_t b, tile;
+  bht::BatchTable* d_tables;
+  bht::BatchItem* d_items;      // fill items, then build items, then find items
+  uint64_t n_fill, n_build, n_find;
+  unsigned int* d_heads;
+  uint32_t* d_status;
+  uint32_t* h_status;
+  const void* build_kernel;
+  const void* find_kernel;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  hipStream_t graph_stream;
+};
+
+struct bht_find_ctx {
+  uint32_t max_requests;
+  uint64_t max_items;
+  bht::BatchTable* d_tables;
+  bht::BatchItem* d_items;
+  unsigned int* d_heads;
+  bht::BatchTable* h_tables;    // pinned staging
+  bht::BatchItem* h_items;
+  hipEvent_t staged;             // the last call's copies are done with the staging
+  bool used;
 };
 
 namespace {
@@ -682,6 +715,304 @@ bht_status bht_diag_cas(void* d_buf, uint64_t bytes, uint64_t n_ops, uint64_t se
       reinterpret_cast<unsigned long long*>(d_sink));
   HIP_TRY(hipGetLastError());
   return BHT_OK;
+}
+
+bht_status bht_batch_create(const bht_batch_entry* entries, uint32_t count, uint32_t item_size,
+                            bht_batch** out) {
+  if (!out || (!entries && count)) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (count == 0) return fail(BHT_ERR_INVALID_ARG, "empty batch");
+  if (item_size == 0) item_size = 8192;
+  if (item_size < 64) return fail(BHT_ERR_INVALID_ARG, "item_size must be at least 64");
+  const bht_table* t0 = entries[0].table;
+  if (!t0) return fail(BHT_ERR_INVALID_ARG, "null table");
+  std::unordered_set<const bht_table*> seen;
+  for (uint32_t i = 0; i < count; ++i) {
+    const bht_batch_entry& e = entries[i];
+    const bht_table* t = e.table;
+    if (!t) return fail(BHT_ERR_INVALID_ARG, "null table in batch");
+    if (!seen.insert(t).second) return fail(BHT_ERR_INVALID_ARG, "table appears twice in batch");
+    if (t->scheme != BHT_BCHT || t->key_bits != 32)
+      return fail(BHT_ERR_UNSUPPORTED, "batches hold 32-bit bucketed cuckoo tables");
+    if (t->b != t0->b || t->tile != t0->tile)
+      return fail(BHT_ERR_INVALID_ARG, "tables of a batch share bucket size and tile width");
+    if (e.n_keys > t->slots) return fail(BHT_ERR_CAPACITY, "more pairs than slots");
+    if ((e.n_keys && (!e.d_keys || !e.d_values)) ||
+        (e.n_queries && (!e.d_queries || !e.d_out_values || !e.d_out_found)))
+      return fail(BHT_ERR_INVALID_ARG, "null data pointer in batch");
+  }
+  const void* bk = nullptr;
+  const void* fk = nullptr;
+#define BHT_BATCH_CASE(B_, W_)                                    \
+  if (t0->b == B_ && t0->tile == W_) {                            \
+    bk = (const void*)batch_build_kernel<B_, W_>;                 \
+    fk = (const void*)batch_find_kernel<B_, W_>;                  \
+  }
+  BHT_BATCH_CASE(8, 4)
+  BHT_BATCH_CASE(8, 8)
+  BHT_BATCH_CASE(16, 4)
+  BHT_BATCH_CASE(16, 8)
+  BHT_BATCH_CASE(16, 16)
+  BHT_BATCH_CASE(32, 8)
+  BHT_BATCH_CASE(32, 16)
+#undef BHT_BATCH_CASE
+  if (!bk) return fail(BHT_ERR_UNSUPPORTED, "no batched kernel for this bucket size and tile");
+
+  std::vector<BatchTable> tables(count);
+  std::vector<BatchItem> fill, build, find;
+  const uint64_t fill_words = 1ull << 16;
+  for (uint32_t i = 0; i < count; ++i) {
+    const bht_batch_entry& e = entries[i];
+    const bht_table* t = e.table;
+    BatchTable& T = tables[i];
+    T.slots = t->d_slots;
+    T.words = t->words;
+    T.keys = e.d_keys;
+    T.vals = e.d_values;
+    T.n_keys = e.n_keys;
+    T.queries = e.d_queries;
+    T.out_v = e.d_out_values;
+    T.out_f = e.d_out_found;
+    T.n_queries = e.n_queries;
+    T.H = make_hash32(t->params, t->m, t->params.num_hashes);
+    T.max_chain = t->params.max_chain;
+    T.rng_seed = t->params.rng_seed;
+    for (uint64_t s = 0; s < t->words; s += fill_words)
+      fill.push_back({i, 0, s, std::min<uint64_t>(fill_words, t->words - s)});
+    for (uint64_t s = 0; s < e.n_keys; s += item_size)
+      build.push_back({i, 0, s, std::min<uint64_t>(item_size, e.n_keys - s)});
+    for (uint64_t s = 0; s < e.n_queries; s += item_size)
+      find.push_back({i, 0, s, std::min<uint64_t>(item_size, e.n_queries - s)});
+  }
+  bht_batch* b = new bht_batch();
+  b->count = count;
+  b->b = t0->b;
+  b->tile = t0->tile;
+  b->build_kernel = bk;
+  b->find_kernel = fk;
+  b->n_fill = fill.size();
+  b->n_build = build.size();
+  b->n_find = find.size();
+  for (uint32_t i = 0; i < count; ++i) {
+    b->tables.push_back(entries[i].table);
+    b->n_keys.push_back(entries[i].n_keys);
+  }
+  std::vector<BatchItem> all(fill);
+  all.insert(all.end(), build.begin(), build.end());
+  all.insert(all.end(), find.begin(), find.end());
+  hipError_t e = hipMalloc(&b->d_tables, sizeof(BatchTable) * count);
+  if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(BatchItem) * std::max<size_t>(1, all.size()));
+  if (e == hipSuccess) e = hipMalloc(&b->d_heads, 16);
+  if (e == hipSuccess) e = hipMalloc(&b->d_status, sizeof(uint32_t) * count);
+  if (e == hipSuccess) e = hipHostMalloc(&b->h_status, sizeof(uint32_t) * count, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_tables, tables.data(), sizeof(BatchTable) * count, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !all.empty())
+    e = hipMemcpy(b->d_items, all.data(), sizeof(BatchItem) * all.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    bht_batch_destroy(b);
+    return fail(BHT_ERR_OOM, std::string("batch arrays: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return BHT_OK;
+}
+
+namespace {
+bht_status batch_launch(bht_batch* b, hipStream_t st) {
+  batch_reset_kernel<<<std::max<uint32_t>(1, std::min<uint32_t>((b->count + 255) / 256, 1024)),
+                       256, 0, st>>>(b->d_heads, b->d_status, b->count);
+  HIP_TRY(hipGetLastError());
+  if (b->n_fill) {
+    batch_fill_kernel<<<(int)std::min<uint64_t>(b->n_fill, 8192), kBlock, 0, st>>>(
+        b->d_tables, b->d_items, b->n_fill);
+    HIP_TRY(hipGetLastError());
+  }
+  if (b->n_build) {
+    const int grid = grid_for(b->build_kernel, b->n_build * kBlock);
+    reinterpret_cast<void (*)(const BatchTable*, const BatchItem*, uint64_t, unsigned int*,
+                              uint32_t*)>(const_cast<void*>(b->build_kernel))
+        <<<grid, kBlock, 0, st>>>(b->d_tables, b->d_items + b->n_fill, b->n_build, b->d_heads,
+                                  b->d_status);
+    HIP_TRY(hipGetLastError());
+  }
+  if (b->n_find) {
+    const int grid = grid_for(b->find_kernel, b->n_find * kBlock);
+    reinterpret_cast<void (*)(const BatchTable*, const BatchItem*, uint64_t, unsigned int*)>(
+        const_cast<void*>(b->find_kernel))
+        <<<grid, kBlock, 0, st>>>(b->d_tables, b->d_items + b->n_fill + b->n_build, b->n_find,
+                                  b->d_heads + 1);
+    HIP_TRY(hipGetLastError());
+  }
+  return BHT_OK;
+}
+}  // namespace
+
+bht_status bht_batch_run(bht_batch* b, void* stream) {
+  if (!b) return fail(BHT_ERR_INVALID_ARG, "null batch");
+  hipStream_t st = as_stream(stream);
+  for (bht_table* t : b->tables) t->built = false;
+  if (st == nullptr) return batch_launch(b, st);
+  if (b->exec && b->graph_stream != st) {
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+  }
+  if (!b->exec) {
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    bht_status s = batch_launch(b, st);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (s != BHT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    b->graph = g;
+    b->graph_stream = st;
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, st));
+  return BHT_OK;
+}
+
+bht_status bht_batch_wait(bht_batch* b, void* stream, bht_status* status_out) {
+  if (!b) return fail(BHT_ERR_INVALID_ARG, "null batch");
+  hipStream_t st = as_stream(stream);
+  HIP_TRY(hipMemcpyAsync(b->h_status, b->d_status, sizeof(uint32_t) * b->count,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  bht_status worst = BHT_OK;
+  for (uint32_t i = 0; i < b->count; ++i) {
+    const uint32_t f = b->h_status[i];
+    bht_status s = BHT_OK;
+    if (f & kFlagSentinel) s = BHT_ERR_SENTINEL_KEY;
+    else if (f & kFlagFailed) s = BHT_ERR_BUILD_FAILED;
+    if (status_out) status_out[i] = s;
+    bht_table* t = b->tables[i];
+    t->built = s == BHT_OK;
+    t->pending = false;
+    t->n_stored = s == BHT_OK ? b->n_keys[i] : 0;
+    if (s != BHT_OK && worst == BHT_OK) worst = s;
+  }
+  if (worst != BHT_OK) g_last_error = "some tables of the batch failed to build";
+  return worst;
+}
+
+void bht_batch_destroy(bht_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_tables) (void)hipFree(b->d_tables);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_heads) (void)hipFree(b->d_heads);
+  if (b->d_status) (void)hipFree(b->d_status);
+  if (b->h_status) (void)hipHostFree(b->h_status);
+  delete b;
+}
+
+bht_status bht_find_ctx_create(uint32_t max_requests, uint64_t max_items, bht_find_ctx** out) {
+  if (!out || max_requests == 0 || max_items == 0) return fail(BHT_ERR_INVALID_ARG, "bad argument");
+  *out = nullptr;
+  bht_find_ctx* c = new bht_find_ctx();
+  c->max_requests = max_requests;
+  c->max_items = max_items;
+  hipError_t e = hipMalloc(&c->d_tables, sizeof(BatchTable) * max_requests);
+  if (e == hipSuccess) e = hipMalloc(&c->d_items, sizeof(BatchItem) * max_items);
+  if (e == hipSuccess) e = hipMalloc(&c->d_heads, 16);
+  if (e == hipSuccess)
+    e = hipHostMalloc(&c->h_tables, sizeof(BatchTable) * max_requests, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(&c->h_items, sizeof(BatchItem) * max_items, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    bht_find_ctx_destroy(c);
+    return fail(BHT_ERR_OOM, std::string("find context: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return BHT_OK;
+}
+
+bht_status bht_multi_find(bht_find_ctx* c, const bht_find_request* reqs, uint32_t count,
+                          uint32_t item_size, void* stream) {
+  if (!c || (!reqs && count)) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  if (count == 0) return BHT_OK;
+  if (count > c->max_requests) return fail(BHT_ERR_CAPACITY, "more requests than the context holds");
+  if (item_size == 0) item_size = 8192;
+  if (item_size < 64) return fail(BHT_ERR_INVALID_ARG, "item_size must be at least 64");
+  const bht_table* t0 = reqs[0].table;
+  if (!t0) return fail(BHT_ERR_INVALID_ARG, "null table");
+  uint64_t items = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    const bht_find_request& r = reqs[i];
+    const bht_table* t = r.table;
+    if (!t) return fail(BHT_ERR_INVALID_ARG, "null table in request");
+    if (!t->built) return fail(BHT_ERR_NOT_BUILT, "request on a table that is not built");
+    if (t->scheme != BHT_BCHT || t->key_bits != 32 || t->b != t0->b || t->tile != t0->tile)
+      return fail(BHT_ERR_UNSUPPORTED, "requests of one call share a 32-bit BCHT configuration");
+    if (r.n && (!r.d_queries || !r.d_out_values || !r.d_out_found))
+      return fail(BHT_ERR_INVALID_ARG, "null data pointer in request");
+    items += (r.n + item_size - 1) / item_size;
+  }
+  if (items > c->max_items) return fail(BHT_ERR_CAPACITY, "more work items than the context holds");
+  const void* fk = nullptr;
+#define BHT_MF_CASE(B_, W_) \
+  if (t0->b == B_ && t0->tile == W_) fk = (const void*)batch_find_kernel<B_, W_>;
+  BHT_MF_CASE(8, 4)
+  BHT_MF_CASE(8, 8)
+  BHT_MF_CASE(16, 4)
+  BHT_MF_CASE(16, 8)
+  BHT_MF_CASE(16, 16)
+  BHT_MF_CASE(32, 8)
+  BHT_MF_CASE(32, 16)
+#undef BHT_MF_CASE
+  if (!fk) return fail(BHT_ERR_UNSUPPORTED, "no query kernel for this bucket size and tile");
+  hipStream_t st = as_stream(stream);
+  // the previous call's copies out of the staging buffers must be finished
+  if (c->used) HIP_TRY(hipEventSynchronize(c->staged));
+  uint64_t k = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    const bht_find_request& r = reqs[i];
+    BatchTable& T = c->h_tables[i];
+    memset(&T, 0, sizeof(T));
+    T.slots = r.table->d_slots;
+    T.words = r.table->words;
+    T.queries = r.d_queries;
+    T.out_v = r.d_out_values;
+    T.out_f = r.d_out_found;
+    T.n_queries = r.n;
+    T.H = make_hash32(r.table->params, r.table->m, r.table->params.num_hashes);
+    for (uint64_t s = 0; s < r.n; s += item_size)
+      c->h_items[k++] = {i, 0, s, std::min<uint64_t>(item_size, r.n - s)};
+  }
+  HIP_TRY(hipMemcpyAsync(c->d_tables, c->h_tables, sizeof(BatchTable) * count,
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c->d_items, c->h_items, sizeof(BatchItem) * k, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(c->staged, st));
+  c->used = true;
+  batch_reset_kernel<<<1, 64, 0, st>>>(c->d_heads, nullptr, 0);
+  HIP_TRY(hipGetLastError());
+  const int grid = grid_for(fk, k * kBlock);
+  reinterpret_cast<void (*)(const BatchTable*, const BatchItem*, uint64_t, unsigned int*)>(
+      const_cast<void*>(fk))<<<grid, kBlock, 0, st>>>(c->d_tables, c->d_items, k, c->d_heads);
+  HIP_TRY(hipGetLastError());
+  return BHT_OK;
+}
+
+void bht_find_ctx_destroy(bht_find_ctx* c) {
+  if (!c) return;
+  if (c->used) (void)hipEventSynchronize(c->staged);
+  if (c->staged) (void)hipEventDestroy(c->staged);
+  if (c->d_tables) (void)hipFree(c->d_tables);
+  if (c->d_items) (void)hipFree(c->d_items);
+  if (c->d_heads) (void)hipFree(c->d_heads);
+  if (c->h_tables) (void)hipHostFree(c->h_tables);
+  if (c->h_items) (void)hipHostFree(c->h_items);
+  delete c;
 }
 
 }  // extern "C"

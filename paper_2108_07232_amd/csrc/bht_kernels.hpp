@@ -317,15 +317,15 @@ struct FindArgs32 {
 
 enum : uint32_t { kRead = 0, kWalk = 1, kEvict = 2 };
 
-// Bucketed cuckoo insertion (Section III-A, Section V-B) for every pair.
+// Bucketed cuckoo insertion (Section III-A, Section V-B) of the pairs in
+// range r by the calling wave.  Returns the status flags this lane raised;
+// *probes accumulates the lane's bucket reads when COUNT.
 template <int B, int W, bool COUNT>
-__global__ __launch_bounds__(kBlock) void cuckoo_build_kernel(BuildArgs32 g) {
+__device__ __forceinline__ uint32_t cuckoo_build_range(const BuildArgs32& g, Range r,
+                                                       uint32_t rng, uint32_t* probes_out) {
   const uint32_t lane = __lane_id();
   const uint32_t tb = lane & ~(uint32_t)(W - 1);
   const uint32_t lt = lane & (uint32_t)(W - 1);
-  const Range r = wave_range(g.n);
-  const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t rng = g.rng_seed ^ (uint32_t)(gtid * 0x9E3779B9ull) ^ (uint32_t)(gtid >> 32);
   if (rng == 0) rng = 0x2545F491u;
 
   Feed<uint32_t> fk, fv;
@@ -397,6 +397,21 @@ __global__ __launch_bounds__(kBlock) void cuckoo_build_kernel(BuildArgs32 g) {
       }
     }
   }
+  if (COUNT) *probes_out += probes;
+  return flags;
+}
+
+// Lane salt for the eviction generator: distinct per lane of the launch.
+__device__ __forceinline__ uint32_t lane_salt() {
+  const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  return (uint32_t)(gtid * 0x9E3779B9ull) ^ (uint32_t)(gtid >> 32);
+}
+
+template <int B, int W, bool COUNT>
+__global__ __launch_bounds__(kBlock) void cuckoo_build_kernel(BuildArgs32 g) {
+  uint32_t probes = 0;
+  const uint32_t flags =
+      cuckoo_build_range<B, W, COUNT>(g, wave_range(g.n), g.rng_seed ^ lane_salt(), &probes);
   if (flags) atomicOr(g.status, flags);
   if (COUNT) {
     const uint32_t total = wave_sum(probes);
@@ -476,11 +491,10 @@ __global__ __launch_bounds__(kBlock) void cuckoo_find_kernel(FindArgs32 g) {
 // then writes the 64 results with one coalesced store each; the next
 // chunk's queries are loaded while the current chunk is probed.
 template <int B, int W, bool COUNT>
-__global__ __launch_bounds__(kBlock) void cuckoo_find_chunk_kernel(FindArgs32 g) {
+__device__ __forceinline__ void cuckoo_find_chunk_range(const FindArgs32& g, Range r) {
   const uint32_t lane = __lane_id();
   const uint32_t tb = lane & ~(uint32_t)(W - 1);
   const uint32_t lt = lane & (uint32_t)(W - 1);
-  const Range r = wave_range(g.n);
   uint32_t q_next = (r.cursor + lane < r.end) ? g.queries[r.cursor + lane] : kEmptyKey;
   for (uint64_t base = r.cursor; base < r.end; base += 64) {
     const uint64_t idx = base + lane;
@@ -516,6 +530,11 @@ __global__ __launch_bounds__(kBlock) void cuckoo_find_chunk_kernel(FindArgs32 g)
       if (COUNT) g.probes[idx] = (uint8_t)rounds;
     }
   }
+}
+
+template <int B, int W, bool COUNT>
+__global__ __launch_bounds__(kBlock) void cuckoo_find_chunk_kernel(FindArgs32 g) {
+  cuckoo_find_chunk_range<B, W, COUNT>(g, wave_range(g.n));
 }
 
 }  // namespace bht
