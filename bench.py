@@ -505,6 +505,8 @@ def run_serve(args):
                 r.done, r.status, r.launch = -1.0, -1, -1
             if mode == "continuous":
                 srv = serve.Server(torch, int(args.budget_gb * 1e9))
+                wk = torch.arange(1, 257, dtype=torch.int32, device="cuda")
+                srv.warmup(wk, wk)
                 for tid, t in enumerate(tables):
                     srv.add_table(tid, t)
                 srv.run(reqs)
@@ -516,6 +518,11 @@ def run_serve(args):
                     bht.bht_find_ctx_destroy(s.ctx)
             else:
                 tabs = dict(enumerate(tables))
+                wk = torch.arange(1, 257, dtype=torch.int32, device="cuda")
+                wt = bht.Table(1024, 16, "bcht", [3, 5, 7], [11, 13, 17])
+                wt.build(wk, wk)
+                wt.find(wk)
+                wt.close()
                 serve.serve_serial(torch, tabs, reqs)
                 launches, evicted = len(reqs), 0
                 for tid in [k for k in tabs if k >= args.initial_tables]:

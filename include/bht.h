@@ -94,7 +94,22 @@ typedef struct {
 bht_status bht_create(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme scheme,
                       const bht_params* params, bht_table** out);
 
-/* Frees the table (NULL is accepted). */
+/* Bytes of device memory a table with these parameters needs (slot array
+ * plus 256 bytes of build status), or 0 for invalid parameters. */
+uint64_t bht_table_bytes(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme scheme,
+                         const bht_params* params);
+
+/* As bht_create, but the table lives in caller-owned device memory
+ * d_buffer of buffer_bytes (at least bht_table_bytes, 256-byte aligned),
+ * for callers whose allocator owns HBM (e.g. a framework's caching
+ * allocator).  The buffer must outlive the table; bht_destroy does not free
+ * it. */
+bht_status bht_create_in(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme scheme,
+                         const bht_params* params, void* d_buffer, uint64_t buffer_bytes,
+                         bht_table** out);
+
+/* Frees the table and, unless it was created with bht_create_in, its
+ * memory (NULL is accepted). */
 void bht_destroy(bht_table* t);
 
 /* Replaces the hash constants and generator seed (after BUILD_FAILED,

@@ -76,6 +76,8 @@ _pp = ctypes.POINTER(ctypes.c_void_p)
 _SIGS = {
     "bht_create": (_st, [_u64, _u32, ctypes.c_int, ctypes.POINTER(bht_params), _pp]),
     "bht_destroy": (None, [_p]),
+    "bht_table_bytes": (_u64, [_u64, _u32, ctypes.c_int, ctypes.POINTER(bht_params)]),
+    "bht_create_in": (_st, [_u64, _u32, ctypes.c_int, ctypes.POINTER(bht_params), _p, _u64, _pp]),
     "bht_reseed": (_st, [_p, ctypes.POINTER(bht_params)]),
     "bht_build": (_st, [_p, _p, _p, _u64, _p]),
     "bht_build_async": (_st, [_p, _p, _p, _u64, _p]),
@@ -170,6 +172,24 @@ def bht_create(capacity_slots: int, bucket_size: int, scheme, params: bht_params
     out = ctypes.c_void_p()
     _check(_lib.bht_create(capacity_slots, bucket_size, scheme, ctypes.byref(params),
                            ctypes.byref(out)), "bht_create")
+    return out
+
+
+def bht_table_bytes(capacity_slots: int, bucket_size: int, scheme, params: bht_params) -> int:
+    if isinstance(scheme, str):
+        scheme = SCHEMES[scheme]
+    return int(_lib.bht_table_bytes(capacity_slots, bucket_size, scheme, ctypes.byref(params)))
+
+
+def bht_create_in(capacity_slots: int, bucket_size: int, scheme, params: bht_params, buffer,
+                  nbytes: int = None):
+    if isinstance(scheme, str):
+        scheme = SCHEMES[scheme]
+    nbytes = buffer.numel() * buffer.element_size() if nbytes is None else nbytes
+    out = ctypes.c_void_p()
+    _check(_lib.bht_create_in(capacity_slots, bucket_size, scheme, ctypes.byref(params),
+                              _dptr(buffer, None, "buffer"), nbytes, ctypes.byref(out)),
+           "bht_create_in")
     return out
 
 
@@ -392,13 +412,17 @@ class Table:
     def __init__(self, capacity_slots: int, bucket_size: int, scheme="bcht", a=(), b=(),
                  key_bits=32, rng_seed=0x9E3779B9, max_chain=128, iht_threshold=0,
                  iht_secondary_b=0, iht_secondary_m=0, tile=None, find_schedule=0,
-                 grid_blocks=0):
+                 grid_blocks=0, buffer=None):
         self.params = make_params(a, b, key_bits=key_bits, rng_seed=rng_seed,
                                   max_chain=max_chain, iht_threshold=iht_threshold,
                                   iht_secondary_b=iht_secondary_b,
                                   iht_secondary_m=iht_secondary_m)
         self.key_bits = key_bits
-        self.handle = bht_create(capacity_slots, bucket_size, scheme, self.params)
+        self.buffer = buffer          # caller-owned device memory kept alive with the table
+        if buffer is None:
+            self.handle = bht_create(capacity_slots, bucket_size, scheme, self.params)
+        else:
+            self.handle = bht_create_in(capacity_slots, bucket_size, scheme, self.params, buffer)
         if tile is not None or find_schedule or grid_blocks:
             bht_set_tuning(self.handle, tile or 0, find_schedule, grid_blocks)
 
@@ -406,6 +430,7 @@ class Table:
         if self.handle:
             bht_destroy(self.handle)
             self.handle = None
+        self.buffer = None
 
     def __del__(self):
         try:

@@ -32,8 +32,9 @@ struct bht_table {
   uint64_t* d_slots;
   uint64_t words;       // uint64 words in the slot array
   uint64_t slots;       // pair capacity (both levels)
-  uint32_t* d_status;   // [0] flags
-  uint32_t* h_status;   // pinned host copy
+  uint32_t* d_status;   // [0] flags; lives after the slot array
+  uint32_t h_status[4]; // host copy
+  bool owns_memory;     // slot array allocated by the library
   uint64_t n_stored;
   uint64_t pending_n;
   bool built;
@@ -423,56 +424,102 @@ uint64_t bht_hash64(uint64_t a, uint64_t b, uint64_t k, uint64_t m) {
   return hash64(a, b, k, UINT64_MAX / m, m);
 }
 
-bht_status bht_create(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme scheme,
-                      const bht_params* params, bht_table** out) {
-  if (!out || !params) return fail(BHT_ERR_INVALID_ARG, "null argument");
-  *out = nullptr;
-  if (bucket_size == 0 || capacity_slots == 0) return fail(BHT_ERR_INVALID_ARG, "zero size");
+}  // extern "C"
+
+namespace {
+
+// Geometry of a table; returns false (with *why) for invalid parameters.
+struct Geometry {
+  uint64_t m, slots, words, slot_bytes, total_bytes;
+};
+
+bool geometry(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme scheme,
+              const bht_params* params, Geometry* g, bht_status* err) {
+  if (!params) return *err = fail(BHT_ERR_INVALID_ARG, "null argument"), false;
+  if (bucket_size == 0 || capacity_slots == 0)
+    return *err = fail(BHT_ERR_INVALID_ARG, "zero size"), false;
   std::string why;
-  if (!valid_params(*params, scheme, bucket_size, &why)) {
-    bool unsupported = why.find("not available") != std::string::npos;
-    return fail(unsupported ? BHT_ERR_UNSUPPORTED : BHT_ERR_INVALID_ARG, why);
-  }
-  const uint64_t m = (capacity_slots + bucket_size - 1) / bucket_size;
-  if (params->key_bits == 32 && m > 0xFFFFFFFFull)
-    return fail(BHT_ERR_INVALID_ARG, "more than 2^32 - 1 buckets");
+  if (!valid_params(*params, scheme, bucket_size, &why))
+    return *err = fail(BHT_ERR_INVALID_ARG, why), false;
+  g->m = (capacity_slots + bucket_size - 1) / bucket_size;
+  if (g->m > 0xFFFFFFFFull) return *err = fail(BHT_ERR_INVALID_ARG, "more than 2^32 - 1 buckets"), false;
+  g->slots = g->m * bucket_size;
+  if (scheme == BHT_IHT && params->iht_secondary_b)
+    g->slots += params->iht_secondary_m * params->iht_secondary_b;
+  g->words = g->slots * (params->key_bits == 64 ? 2 : 1);
+  g->slot_bytes = (g->words * sizeof(uint64_t) + 255) / 256 * 256;
+  g->total_bytes = g->slot_bytes + 256;          // + the build status words
+  return true;
+}
+
+bht_status create_common(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme scheme,
+                         const bht_params* params, void* buffer, uint64_t buffer_bytes,
+                         bht_table** out) {
+  if (!out) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  Geometry g;
+  bht_status err = BHT_OK;
+  if (!geometry(capacity_slots, bucket_size, scheme, params, &g, &err)) return err;
   bht_table* t = new bht_table();
   t->scheme = scheme;
   t->b = bucket_size;
-  t->m = m;
+  t->m = g.m;
   t->key_bits = params->key_bits;
   t->params = *params;
   t->tile = default_tile(scheme, bucket_size);
-  const uint64_t slot_words = params->key_bits == 64 ? 2 : 1;
-  t->slots = m * bucket_size;
-  if (scheme == BHT_IHT && params->iht_secondary_b)
-    t->slots += params->iht_secondary_m * params->iht_secondary_b;
-  t->words = t->slots * slot_words;
+  t->slots = g.slots;
+  t->words = g.words;
   hipError_t e = hipGetDevice(&t->device);
-  if (e == hipSuccess) e = hipMalloc(&t->d_slots, t->words * sizeof(uint64_t));
   if (e != hipSuccess) {
     delete t;
-    return fail(BHT_ERR_OOM, std::string("slot array: ") + hipGetErrorString(e));
+    return hip_fail(e, "hipGetDevice");
   }
-  e = hipMalloc(&t->d_status, 16);
-  if (e == hipSuccess) e = hipHostMalloc(&t->h_status, 16, hipHostMallocDefault);
-  if (e != hipSuccess) {
-    (void)hipFree(t->d_slots);
-    if (t->d_status) (void)hipFree(t->d_status);
+  char* base = static_cast<char*>(buffer);
+  if (!buffer) {
+    e = hipMalloc(&base, g.total_bytes);
+    if (e != hipSuccess) {
+      delete t;
+      return fail(BHT_ERR_OOM, std::string("slot array: ") + hipGetErrorString(e));
+    }
+    t->owns_memory = true;
+  } else if (buffer_bytes < g.total_bytes || (reinterpret_cast<uintptr_t>(buffer) & 255)) {
     delete t;
-    return fail(BHT_ERR_OOM, std::string("status word: ") + hipGetErrorString(e));
+    return fail(BHT_ERR_INVALID_ARG, "buffer too small or not 256-byte aligned");
   }
+  t->d_slots = reinterpret_cast<uint64_t*>(base);
+  t->d_status = reinterpret_cast<uint32_t*>(base + g.slot_bytes);
   *out = t;
   return BHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t bht_table_bytes(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme scheme,
+                         const bht_params* params) {
+  Geometry g;
+  bht_status err;
+  return geometry(capacity_slots, bucket_size, scheme, params, &g, &err) ? g.total_bytes : 0;
+}
+
+bht_status bht_create(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme scheme,
+                      const bht_params* params, bht_table** out) {
+  return create_common(capacity_slots, bucket_size, scheme, params, nullptr, 0, out);
+}
+
+bht_status bht_create_in(uint64_t capacity_slots, uint32_t bucket_size, bht_scheme scheme,
+                         const bht_params* params, void* d_buffer, uint64_t buffer_bytes,
+                         bht_table** out) {
+  if (!d_buffer) return fail(BHT_ERR_INVALID_ARG, "null buffer");
+  return create_common(capacity_slots, bucket_size, scheme, params, d_buffer, buffer_bytes, out);
 }
 
 void bht_destroy(bht_table* t) {
   if (!t) return;
   if (t->timing)
     for (int i = 0; i < 4; ++i) (void)hipEventDestroy(t->ev[i]);
-  (void)hipFree(t->d_slots);
-  (void)hipFree(t->d_status);
-  (void)hipHostFree(t->h_status);
+  if (t->owns_memory) (void)hipFree(t->d_slots);
   delete t;
 }
 
@@ -960,8 +1007,12 @@ bht_status bht_multi_find(bht_find_ctx* c, const bht_find_request* reqs, uint32_
   }
   if (items > c->max_items) return fail(BHT_ERR_CAPACITY, "more work items than the context holds");
   const void* fk = nullptr;
-#define BHT_MF_CASE(B_, W_) \
-  if (t0->b == B_ && t0->tile == W_) fk = (const void*)batch_find_kernel<B_, W_>;
+  const void* ik = nullptr;
+#define BHT_MF_CASE(B_, W_)                              \
+  if (t0->b == B_ && t0->tile == W_) {                   \
+    fk = (const void*)batch_find_kernel<B_, W_>;         \
+    ik = (const void*)inline_find_kernel<B_, W_>;        \
+  }
   BHT_MF_CASE(8, 4)
   BHT_MF_CASE(8, 8)
   BHT_MF_CASE(16, 4)
@@ -971,6 +1022,39 @@ bht_status bht_multi_find(bht_find_ctx* c, const bht_find_request* reqs, uint32_
   BHT_MF_CASE(32, 16)
 #undef BHT_MF_CASE
   if (!fk) return fail(BHT_ERR_UNSUPPORTED, "no query kernel for this bucket size and tile");
+  if (count <= (uint32_t)kInlineRequests && items <= 0xFFFFFFFFull) {
+    // Spread a small launch over the resident waves: shrink the item (down
+    // to one 64-query chunk) until every wave has about one item.
+    uint64_t total_q = 0;
+    for (uint32_t i = 0; i < count; ++i) total_q += reqs[i].n;
+    const uint64_t waves = (uint64_t)grid_for(ik, 1ull << 40) * (kBlock / 64);
+    const uint64_t even = ((total_q + waves - 1) / waves + 63) / 64 * 64;
+    item_size = (uint32_t)std::max<uint64_t>(64, std::min<uint64_t>(item_size, even));
+    InlineFind arg;
+    memset(&arg, 0, sizeof(arg));
+    uint32_t first = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+      const bht_find_request& r = reqs[i];
+      FindTable& T = arg.t[i];
+      T.slots = r.table->d_slots;
+      T.queries = r.d_queries;
+      T.out_v = r.d_out_values;
+      T.out_f = r.d_out_found;
+      T.n = r.n;
+      T.H = make_hash32(r.table->params, r.table->m, r.table->params.num_hashes);
+      arg.first_item[i] = first;
+      first += (uint32_t)((r.n + item_size - 1) / item_size);
+    }
+    arg.first_item[count] = first;
+    arg.count = count;
+    arg.item_size = item_size;
+    if (first == 0) return BHT_OK;
+    const int grid = grid_for(ik, (uint64_t)first * kBlock);
+    reinterpret_cast<void (*)(InlineFind)>(const_cast<void*>(ik))
+        <<<grid, kBlock, 0, as_stream(stream)>>>(arg);
+    HIP_TRY(hipGetLastError());
+    return BHT_OK;
+  }
   hipStream_t st = as_stream(stream);
   // the previous call's copies out of the staging buffers must be finished
   if (c->used) HIP_TRY(hipEventSynchronize(c->staged));

@@ -123,4 +123,51 @@ __global__ __launch_bounds__(kBlock) void batch_find_kernel(const BatchTable* __
   }
 }
 
+// Small coalesced query launches pass their request descriptors as kernel
+// arguments (no staging copy, no queue reset): a launch is then as cheap as
+// a single-table query.  Work items are implicit: request r owns items
+// [first_item[r], first_item[r+1]), each item_size queries long, and waves
+// take items round-robin.
+struct FindTable {
+  const uint64_t* slots;
+  const uint32_t* queries;
+  uint32_t* out_v;
+  uint8_t* out_f;
+  uint64_t n;
+  Hash32 H;
+};
+
+constexpr int kInlineRequests = 24;
+
+struct InlineFind {
+  FindTable t[kInlineRequests];
+  uint32_t first_item[kInlineRequests + 1];
+  uint32_t count;
+  uint32_t item_size;
+};
+
+template <int B, int W>
+__global__ __launch_bounds__(kBlock) void inline_find_kernel(InlineFind a) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  const uint32_t total = a.first_item[a.count];
+  for (uint64_t it = wave; it < total; it += nwaves) {
+    uint32_t r = 0;
+    while (r + 1 < a.count && a.first_item[r + 1] <= it) ++r;
+    const FindTable& T = a.t[r];
+    FindArgs32 g;
+    g.slots = T.slots;
+    g.queries = T.queries;
+    g.n = T.n;
+    g.out_v = T.out_v;
+    g.out_f = T.out_f;
+    g.probes = nullptr;
+    g.H = T.H;
+    Range rg;
+    rg.cursor = (uint64_t)(it - a.first_item[r]) * a.item_size;
+    rg.end = rg.cursor + a.item_size < T.n ? rg.cursor + a.item_size : T.n;
+    cuckoo_find_chunk_range<B, W, false>(g, rg);
+  }
+}
+
 }  // namespace bht

@@ -47,9 +47,10 @@ class Request:
 class _Slot:
     stream: object
     ctx: object
-    event: object = None
+    event: object = None            # set while a launch is in flight
     requests: list = field(default_factory=list)
     kind: str = ""
+    done_event: object = None       # reused for every launch of this slot
 
 
 class Server:
@@ -72,6 +73,9 @@ class Server:
         self.lookup_slots = [_Slot(torch.cuda.Stream(), bht.bht_find_ctx_create(max_batch, max_items))
                              for _ in range(streams)]
         self.build_slots = [_Slot(torch.cuda.Stream(), None) for _ in range(build_streams)]
+        for slot in self.lookup_slots + self.build_slots:
+            slot.done_event = torch.cuda.Event()
+        self.building = set()                        # ids with a build waiting or running
 
     def close(self):
         self.torch.cuda.synchronize()
@@ -80,6 +84,29 @@ class Server:
         for t in self.tables.values():
             t.close()
         self.tables.clear()
+
+    def warmup(self, keys, vals):
+        """Runs one build and one coalesced lookup on every stream so that
+        kernel code objects and allocator pools are loaded before timing.
+        keys / vals: a few device key-value pairs (int32 bits)."""
+        torch = self.torch
+        for slot in self.build_slots:
+            with torch.cuda.stream(slot.stream):
+                params = bht.make_params([3, 5, 7], [11, 13, 17])
+                nbytes = bht.bht_table_bytes(4 * keys.numel(), self.bucket, "bcht", params)
+                buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+                t = bht.Table(4 * keys.numel(), self.bucket, "bcht", [3, 5, 7], [11, 13, 17],
+                              buffer=buf)
+                bht.bht_build_async(t.handle, keys, vals, stream=slot.stream)
+                bht.bht_build_wait(t.handle, stream=slot.stream)
+                for ls in self.lookup_slots:
+                    ov = torch.empty(keys.numel(), dtype=torch.int32, device="cuda")
+                    of = torch.empty(keys.numel(), dtype=torch.uint8, device="cuda")
+                    bht.bht_multi_find(ls.ctx, [(t.handle, keys, ov, of)], self.item_size,
+                                       stream=ls.stream)
+                    ls.stream.synchronize()
+                t.close()
+        torch.cuda.synchronize()
 
     # ------------------------------------------------------------- tables
 
@@ -114,6 +141,7 @@ class Server:
                     req = slot.requests[0]
                     st = bht.bht_build_wait(self.tables[req.table].handle, stream=slot.stream)
                     req.status = st
+                    self.building.discard(req.table)
                     if st == bht.BHT_OK:
                         self.ready.add(req.table)
                     else:
@@ -152,6 +180,7 @@ class Server:
                 r = requests[nxt]
                 if r.kind == "build":
                     pending_builds.append(r)
+                    self.building.add(r.table)
                 else:
                     self.pins[r.table] += 1
                     pending_lookups.append(r)
@@ -164,21 +193,25 @@ class Server:
                     if not self._make_room(m * self.bucket * 8):
                         break
                     pending_builds.popleft()
-                    table = bht.Table(r.capacity, self.bucket, "bcht", r.a, r.c, rng_seed=r.rng_seed)
-                    self.tables[r.table] = table
-                    self.bytes += table.info[3]
+                    params = bht.make_params(r.a, r.c, rng_seed=r.rng_seed)
+                    nbytes = bht.bht_table_bytes(r.capacity, self.bucket, "bcht", params)
                     with torch.cuda.stream(slot.stream):
+                        # table memory from the framework's caching allocator
+                        buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+                        table = bht.Table(r.capacity, self.bucket, "bcht", r.a, r.c,
+                                          rng_seed=r.rng_seed, buffer=buf)
+                        self.tables[r.table] = table
+                        self.bytes += table.info[3]
                         bht.bht_build_async(table.handle, r.keys, r.vals, stream=slot.stream)
-                        ev = torch.cuda.Event()
-                        ev.record(slot.stream)
-                    slot.event, slot.requests, slot.kind = ev, [r], "build"
+                        slot.done_event.record(slot.stream)
+                    slot.event, slot.requests, slot.kind = slot.done_event, [r], "build"
                     r.launch = self.launches
                     self.launches += 1
             # lookups: every ready one, coalesced, on a free stream
             if pending_lookups:
                 slot = next((s for s in self.lookup_slots if s.event is None), None)
                 if slot is not None:
-                    building = {b.table for b in pending_builds}
+                    building = self.building
                     batch, keep = [], collections.deque()
                     while pending_lookups:
                         r = pending_lookups.popleft()
@@ -197,11 +230,9 @@ class Server:
                             self.tables.move_to_end(r.table)
                             reqs.append((self.tables[r.table].handle, r.queries, r.out_v, r.out_f))
                             r.launch = self.launches
-                        with torch.cuda.stream(slot.stream):
-                            bht.bht_multi_find(slot.ctx, reqs, self.item_size, stream=slot.stream)
-                            ev = torch.cuda.Event()
-                            ev.record(slot.stream)
-                        slot.event, slot.requests, slot.kind = ev, batch, "lookup"
+                        bht.bht_multi_find(slot.ctx, reqs, self.item_size, stream=slot.stream)
+                        slot.done_event.record(slot.stream)
+                        slot.event, slot.requests, slot.kind = slot.done_event, batch, "lookup"
                         self.launches += 1
             completed += self._poll(now)
         torch.cuda.synchronize()
