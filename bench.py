@@ -32,7 +32,9 @@ def parse():
                     help="serve workload: arrival rates (requests/s), comma separated")
     ap.add_argument("--initial-tables", type=int, default=512)
     ap.add_argument("--budget-gb", type=float, default=64.0)
-    ap.add_argument("--workload", default="bcht", choices=["bcht", "schemes", "batched", "serve"],
+    ap.add_argument("--runs", type=int, default=200, help="success workload: builds per load factor")
+    ap.add_argument("--workload", default="bcht",
+                    choices=["bcht", "schemes", "batched", "serve", "success"],
                     help="bcht: the headline BCHT workload; schemes: the comparison of "
                          "BCHT, BP2HT, two-level iceberg, 1CHT and 64-bit BCHT")
     ap.add_argument("--steps", type=int, default=5)
@@ -549,12 +551,70 @@ def run_serve(args):
             f.write(line + "\n")
 
 
+SUCCESS_SWEEP = [
+    # name, scheme, slots per bucket, hashes, iceberg threshold, load factors
+    ("bcht_b16", "bcht", 16, 3, 0, (0.95, 0.96, 0.97, 0.98, 0.99)),
+    ("bp2ht_b32", "bp2ht", 32, 2, 0, (0.88, 0.89, 0.90, 0.91, 0.92)),
+    ("iht_b32_t80", "iht", 32, 3, 25, (0.88, 0.89, 0.90, 0.91, 0.92)),
+    ("cht1_h4", "cht1", 1, 4, 0, (0.85, 0.86, 0.87, 0.88, 0.89)),
+]
+
+
+def run_success(args):
+    """Build success rate (Section VII-D): the same keys built with `runs`
+    different hash-constant sets per load factor; reports the fraction that
+    succeed and the highest load factor with at least 99% success."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2108_07232_amd as bht
+    n = 1 << args.log2n
+    dev = torch.device("cuda", 0)
+    keys = torch.from_numpy(datagen.unique_keys(n, args.seed).view(np.int32)).to(dev)
+    vals = torch.from_numpy(datagen.values(n, args.seed).view(np.int32)).to(dev)
+    out = {"workload": "success", "n_keys": n, "runs_per_load_factor": args.runs, "schemes": {}}
+    for name, scheme, b, h, thr, lfs in SUCCESS_SWEEP:
+        rates = {}
+        for lf in lfs:
+            cap = datagen.capacity_for(n, lf)
+            ok = 0
+            table = None
+            for run in range(args.runs):
+                s = args.seed * 100003 + run
+                a, c = datagen.hash_constants(s, h)
+                if table is None:
+                    table = bht.Table(cap, b, scheme, a, c, rng_seed=datagen.rng_seed(s),
+                                      iht_threshold=thr)
+                else:
+                    bht.bht_reseed(table.handle, bht.make_params(a, c, rng_seed=datagen.rng_seed(s),
+                                                                 iht_threshold=thr))
+                ok += table.build(keys, vals) == bht.BHT_OK
+            table.close()
+            rates[str(lf)] = round(ok / args.runs, 4)
+            log("success %s LF %.2f: %d/%d" % (name, lf, ok, args.runs))
+        good = [float(lf) for lf, r in rates.items() if r >= 0.99]
+        out["schemes"][name] = {"success": rates, "max_lf_99pct": max(good) if good else None}
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "a") as f:
+            f.write(line + "\n")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "success":
+        import torch
+        torch.cuda.set_device(0)
+        if args.log2n == 28:
+            args.log2n = 24
+        run_success(args)
+        return
     if args.workload == "serve":
         import torch
         torch.cuda.set_device(0)

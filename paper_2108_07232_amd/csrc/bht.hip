@@ -738,7 +738,8 @@ bht_status bht_diag_gather(const void* d_buf, uint64_t bytes, uint64_t n_reads, 
   const uint64_t* buf = static_cast<const uint64_t*>(d_buf);
   auto sink = reinterpret_cast<unsigned long long*>(d_sink);
   hipStream_t st = as_stream(stream);
-  const uint64_t units = bytes / line_bytes;
+  const uint64_t units64 = bytes / line_bytes;
+  const uint32_t units = (uint32_t)std::min<uint64_t>(units64, 0xFFFFFFFFull);
 #define BHT_GATHER(LB)                                                              \
   if (line_bytes == LB) {                                                           \
     const int grid = grid_for((const void*)diag_gather_kernel<LB>, 1ull << 40);     \
@@ -758,7 +759,8 @@ bht_status bht_diag_cas(void* d_buf, uint64_t bytes, uint64_t n_ops, uint64_t se
   if (!d_buf || !d_sink || bytes < 8) return fail(BHT_ERR_INVALID_ARG, "bad buffer");
   const int grid = grid_for((const void*)diag_cas_kernel, 1ull << 40);
   diag_cas_kernel<<<grid, kBlock, 0, as_stream(stream)>>>(
-      static_cast<uint64_t*>(d_buf), bytes / 8, n_ops, seed,
+      static_cast<uint64_t*>(d_buf), (uint32_t)std::min<uint64_t>(bytes / 8, 0xFFFFFFFFull), n_ops,
+      seed,
       reinterpret_cast<unsigned long long*>(d_sink));
   HIP_TRY(hipGetLastError());
   return BHT_OK;

@@ -17,18 +17,21 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 // Random reads of LB-byte aligned blocks (LB / 16 lanes x 16 bytes each)
 // with no table logic: at LB = 128 the access pattern of one bucket probe,
 // hence the practical ceiling for probes on a buffer of this size.
+// The block index costs a few integer operations (no division), so the
+// loop is bound by memory, not by index arithmetic.
 template <int LB>
 __global__ __launch_bounds__(kBlock) void diag_gather_kernel(const uint64_t* __restrict__ buf,
-                                                            uint64_t units, uint64_t reads,
+                                                            uint32_t units, uint64_t reads,
                                                             uint64_t seed,
                                                             unsigned long long* __restrict__ sink) {
   constexpr int W = LB / 16;
   const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t tiles = ((uint64_t)gridDim.x * blockDim.x) / W;
   const uint32_t lt = threadIdx.x % W;
+  const uint64_t M = fastmod32_constant(units);
   uint64_t acc = 0;
   for (uint64_t r = gtid / W; r < reads; r += tiles) {
-    const uint64_t u = mix64(r ^ seed) % units;
+    const uint64_t u = fastmod32((uint32_t)mix64(r ^ seed), M, units);
     const u64x2 v = reinterpret_cast<const u64x2*>(buf + u * (LB / 8))[lt];
     acc ^= v.x ^ v.y;
   }
@@ -38,14 +41,15 @@ __global__ __launch_bounds__(kBlock) void diag_gather_kernel(const uint64_t* __r
 // Random 8-byte compare-and-swaps that never change memory (the swapped-in
 // value equals the expected one): the device's rate for slot atomics.
 __global__ __launch_bounds__(kBlock) void diag_cas_kernel(uint64_t* __restrict__ buf,
-                                                         uint64_t slots, uint64_t ops,
+                                                         uint32_t slots, uint64_t ops,
                                                          uint64_t seed,
                                                          unsigned long long* __restrict__ sink) {
   const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t M = fastmod32_constant(slots);
   uint64_t acc = 0;
   for (uint64_t r = gtid; r < ops; r += stride) {
-    const uint64_t s = mix64(r ^ seed) % slots;
+    const uint64_t s = fastmod32((uint32_t)mix64(r ^ seed), M, slots);
     acc ^= cas64(buf + s, 0x5555555555555555ull, 0x5555555555555555ull);
   }
   if (acc == 0x9E3779B97F4A7C15ull) atomicAdd(sink, 1ull);
