@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--runs", type=int, default=200, help="success workload: builds per load factor")
     ap.add_argument("--workload", default="bcht",
-                    choices=["bcht", "schemes", "batched", "serve", "success"],
+                    choices=["bcht", "lfsweep", "schemes", "batched", "serve", "success"],
                     help="bcht: the headline BCHT workload; schemes: the comparison of "
                          "BCHT, BP2HT, two-level iceberg, 1CHT and 64-bit BCHT")
     ap.add_argument("--steps", type=int, default=5)
@@ -560,6 +560,112 @@ SUCCESS_SWEEP = [
 ]
 
 
+LF_SWEEP = (0.6, 0.7, 0.8, 0.9, 0.95, 0.99)
+
+
+def run_lfsweep(args):
+    """Load-factor sweep of the BCHT workload (b = 16, h = 3): for each load
+    factor, build rate and query rates at 100/0/50% positive (kernel time,
+    mean over the timed steps) and the average probes per key counted by the
+    instrumented kernels (untimed runs).  A load factor whose builds keep
+    failing with the 128-step eviction cap is run with a longer cap, and the
+    cap used is reported."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2108_07232_amd as bht
+
+    n = 1 << args.log2n
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    log("lf sweep: generating 2^%d inputs" % args.log2n)
+    keys, vals = datagen.unique_keys(n, args.seed), datagen.values(n, args.seed)
+    d_keys = torch.from_numpy(keys.view(np.int32)).to(dev)
+    d_vals = torch.from_numpy(vals.view(np.int32)).to(dev)
+    del keys, vals
+    d_q = {}
+    for qname, frac in (("find_pos", 1.0), ("find_neg", 0.0), ("find_mix", 0.5)):
+        q = datagen.mixed_queries(n, n, frac, args.seed)
+        d_q[qname] = torch.from_numpy(q.view(np.int32)).to(dev)
+    out_v = torch.empty(n, dtype=torch.int32, device=dev)
+    out_f = torch.empty(n, dtype=torch.uint8, device=dev)
+    results = []
+    seed = args.seed
+    for lf in LF_SWEEP:
+        cap = datagen.capacity_for(n, lf)
+        table, failures, max_chain = None, 0, 128
+        while table is None and max_chain <= 4096:
+            for _ in range(5):
+                a, c = datagen.hash_constants(seed, 3)
+                t = bht.Table(cap, args.bucket, "bcht", a, c, rng_seed=datagen.rng_seed(seed),
+                              max_chain=max_chain)
+                seed += 7919
+                if t.build(d_keys, d_vals) == bht.BHT_OK:
+                    table = t
+                    break
+                failures += 1
+                t.close()
+            if table is None:
+                log("lf %.2f: no build with eviction cap %d" % (lf, max_chain))
+                max_chain *= 8
+        if table is None:
+            results.append({"load_factor": lf, "built": False, "build_failures": failures})
+            continue
+        bht.bht_enable_timing(table.handle, True)
+        ms = {"build": [], "find_pos": [], "find_neg": [], "find_mix": []}
+        timed_failures = 0
+        for step in range(args.warmup + args.steps):
+            while table.build(d_keys, d_vals) != bht.BHT_OK:
+                timed_failures += 1
+                if timed_failures > 50:
+                    raise RuntimeError("lf %.2f: builds keep failing" % lf)
+                a, c = datagen.hash_constants(seed, 3)
+                seed += 7919
+                bht.bht_reseed(table.handle, bht.make_params(
+                    a, c, rng_seed=datagen.rng_seed(seed), max_chain=max_chain))
+            build_ms = bht.bht_kernel_ms(table.handle)[0]
+            find_ms = {}
+            for qname in ("find_pos", "find_neg", "find_mix"):
+                bht.bht_find(table.handle, d_q[qname], out_v, out_f, stream=stream)
+                find_ms[qname] = bht.bht_kernel_ms(table.handle)[1]
+            if step >= args.warmup:
+                ms["build"].append(build_ms)
+                for k, v in find_ms.items():
+                    ms[k].append(v)
+        total = torch.zeros(1, dtype=torch.int64, device=dev)
+        st = bht.bht_build_counted(table.handle, d_keys, d_vals, total)
+        probes = {"insert": int(total.item()) / n if st == bht.BHT_OK else None}
+        pr = torch.empty(n, dtype=torch.uint8, device=dev)
+        for qname in ("find_pos", "find_neg", "find_mix"):
+            bht.bht_find_counted(table.handle, d_q[qname], out_v, out_f, pr, stream=stream)
+            probes[qname.replace("find_", "")] = float(pr.sum(dtype=torch.int64).item()) / n
+        m, b, _, table_bytes = table.info
+        entry = {"load_factor": lf, "actual_load_factor": round(n / (m * b), 6), "buckets": m,
+                 "table_bytes": table_bytes, "max_chain": max_chain,
+                 "build_failures": failures + timed_failures,
+                 "probes_per_key": {k: (round(v, 4) if v is not None else None)
+                                    for k, v in probes.items()}}
+        for k, v in ms.items():
+            avg = float(np.mean(v))
+            entry[k + "_ms"] = round(avg, 4)
+            entry[k + "_gkeys_s"] = round(n / (avg * 1e-3) / 1e9, 4)
+        if probes["insert"] is not None:
+            bytes_per = algorithmic_bytes(probes)
+            entry["model_gbs"] = {k: round(bytes_per[k] * n / (entry[k + "_ms"] * 1e-3) / 1e9, 1)
+                                  for k in bytes_per}
+        results.append(entry)
+        log("lf %.2f: %s" % (lf, json.dumps(entry)))
+        table.close()
+        torch.cuda.empty_cache()
+    line = json.dumps({"workload": "lfsweep", "n_keys": n, "bucket_slots": args.bucket,
+                       "hashes": 3, "results": results})
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "a") as f:
+            f.write(line + "\n")
+
+
 def run_success(args):
     """Build success rate (Section VII-D): the same keys built with `runs`
     different hash-constant sets per load factor; reports the fraction that
@@ -614,6 +720,11 @@ def main():
         if args.log2n == 28:
             args.log2n = 24
         run_success(args)
+        return
+    if args.workload == "lfsweep":
+        import torch
+        torch.cuda.set_device(0)
+        run_lfsweep(args)
         return
     if args.workload == "serve":
         import torch

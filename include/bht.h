@@ -132,6 +132,30 @@ bht_status bht_build_async(bht_table* t, const uint32_t* d_keys, const uint32_t*
                            uint64_t n, void* stream);
 bht_status bht_build_wait(bht_table* t, void* stream);
 
+/* Fills *out with a parameter set for `scheme` drawn from `seed`: the
+ * scheme's default hash count (BP2HT 2, others 3), hash constants a_i
+ * uniform in [1, p-1] and b_i uniform in [0, p-1] (Section VII: randomly
+ * generated constants; p = 4294967291 for 32-bit keys, 2^61 - 1 for 64-bit
+ * keys), a nonzero eviction generator seed and the 128-step eviction cap;
+ * IHT threshold and secondary level are left 0 (one level, default
+ * threshold).  All four constant pairs are drawn, so num_hashes may be
+ * raised afterwards.  Deterministic in seed; key_bits must be 32 or 64. */
+bht_status bht_params_from_seed(uint64_t seed, bht_scheme scheme, uint32_t key_bits,
+                                bht_params* out);
+
+/* Build with automatic reseeding (Section VII: a build that fails is
+ * repeated with new hash constants).  Runs bht_build (32-bit tables) or
+ * bht_build64 (64-bit tables; d_keys, d_values then point to uint64) with
+ * the table's current parameters; after each BUILD_FAILED it replaces the
+ * hash constants and generator seed by the draw of bht_params_from_seed for
+ * seed + attempt - 1 (all other parameters kept) and builds again, at most
+ * max_attempts builds in total (>= 1).  Returns the last build's status;
+ * *attempts_out (may be NULL) receives the number of builds run.  The table
+ * keeps the constants of the last attempt.  Synchronous, like bht_build. */
+bht_status bht_build_retry(bht_table* t, const void* d_keys, const void* d_values, uint64_t n,
+                           uint64_t seed, uint32_t max_attempts, uint32_t* attempts_out,
+                           void* stream);
+
 /* Bulk find of n queries (Section III; Section V).  d_out_values[i] is the
  * value stored with d_queries[i], or 0xFFFFFFFF when absent; d_out_found[i]
  * is 1 when present, else 0.  Asynchronous on stream; the table must be

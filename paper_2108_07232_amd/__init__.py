@@ -86,6 +86,8 @@ _SIGS = {
     "bht_build64": (_st, [_p, _p, _p, _u64, _p]),
     "bht_find64": (_st, [_p, _p, _u64, _p, _p, _p]),
     "bht_build_counted": (_st, [_p, _p, _p, _u64, _p, _p]),
+    "bht_params_from_seed": (_st, [_u64, ctypes.c_int, _u32, ctypes.POINTER(bht_params)]),
+    "bht_build_retry": (_st, [_p, _p, _p, _u64, _u64, _u32, ctypes.POINTER(_u32), _p]),
     "bht_find_counted": (_st, [_p, _p, _u64, _p, _p, _p, _p]),
     "bht_set_tuning": (_st, [_p, ctypes.POINTER(bht_tuning)]),
     "bht_get_tuning": (_st, [_p, ctypes.POINTER(bht_tuning)]),
@@ -245,6 +247,27 @@ def bht_find64(table, queries, out_values, out_found, n=None, stream=None):
     _check(_lib.bht_find64(table, _dptr(queries, None, "queries"), n,
                            _dptr(out_values, None, "out_values"),
                            _dptr(out_found, None, "out_found"), _stream(stream)), "bht_find64")
+
+
+def bht_params_from_seed(seed: int, scheme, key_bits: int = 32) -> bht_params:
+    if isinstance(scheme, str):
+        scheme = SCHEMES[scheme]
+    p = bht_params()
+    _check(_lib.bht_params_from_seed(seed & (2**64 - 1), scheme, key_bits, ctypes.byref(p)),
+           "bht_params_from_seed")
+    return p
+
+
+def bht_build_retry(table, keys, values, seed: int, max_attempts: int = 50, n=None, stream=None):
+    """Returns (status, builds run)."""
+    n = keys.numel() if n is None else n
+    attempts = _u32(0)
+    st = _lib.bht_build_retry(table, _dptr(keys, None, "keys"), _dptr(values, None, "values"), n,
+                              seed & (2**64 - 1), max_attempts, ctypes.byref(attempts),
+                              _stream(stream))
+    if st not in (BHT_OK, BHT_ERR_BUILD_FAILED, BHT_ERR_SENTINEL_KEY):
+        _check(st, "bht_build_retry")
+    return st, attempts.value
 
 
 def bht_build_counted(table, keys, values, probe_total, n=None, stream=None) -> int:

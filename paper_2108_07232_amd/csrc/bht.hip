@@ -153,6 +153,36 @@ Hash32 make_hash32(const bht_params& p, uint64_t m, uint32_t h) {
   return H;
 }
 
+// splitmix64 (Steele, Lea, Flood; "Fast splittable pseudorandom number
+// generators", 2014): the stream from which seeded hash constants are drawn.
+uint64_t splitmix64_next(uint64_t* state) {
+  uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Section VII draws the hash constants at random: a_i uniform in [1, p-1] and
+// b_i uniform in [0, p-1], by rejection from the seed's stream (32-bit draws
+// for p = 2^32 - 5, 61-bit draws for p = 2^61 - 1); the eviction generator
+// seed is the next nonzero 32-bit draw.  All four hash slots are filled.
+void draw_constants(uint64_t seed, uint32_t key_bits, uint64_t a[4], uint64_t b[4],
+                    uint32_t* rng_seed) {
+  uint64_t st = seed ^ 0x5EEDC0457A27ull;
+  const uint64_t prime = key_bits == 64 ? kP61 : kP32;
+  const int shift = key_bits == 64 ? 3 : 32;
+  for (int i = 0; i < 4; ++i) {
+    uint64_t x;
+    do x = splitmix64_next(&st) >> shift; while (x == 0 || x >= prime);
+    a[i] = x;
+    do x = splitmix64_next(&st) >> shift; while (x >= prime);
+    b[i] = x;
+  }
+  uint32_t r;
+  do r = (uint32_t)(splitmix64_next(&st) >> 32); while (r == 0);
+  *rng_seed = r;
+}
+
 bool valid_params(const bht_params& p, bht_scheme scheme, uint32_t b, std::string* why) {
   if (p.key_bits != 32 && p.key_bits != 64) return *why = "key_bits must be 32 or 64", false;
   const uint64_t prime = p.key_bits == 32 ? kP32 : kP61;
@@ -558,6 +588,49 @@ bht_status bht_build(bht_table* t, const uint32_t* d_keys, const uint32_t* d_val
   bht_status s = build32_enqueue(t, d_keys, d_values, n, nullptr, stream);
   if (s != BHT_OK) return s;
   return bht_build_wait(t, stream);
+}
+
+bht_status bht_params_from_seed(uint64_t seed, bht_scheme scheme, uint32_t key_bits,
+                                bht_params* out) {
+  if (!out) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  if (key_bits != 32 && key_bits != 64) return fail(BHT_ERR_INVALID_ARG, "key_bits must be 32 or 64");
+  bht_params p{};
+  switch (scheme) {
+    case BHT_BP2HT: p.num_hashes = 2; break;
+    case BHT_BCHT: case BHT_IHT: case BHT_CHT1: p.num_hashes = 3; break;
+    default: return fail(BHT_ERR_INVALID_ARG, "unknown scheme");
+  }
+  p.key_bits = key_bits;
+  p.max_chain = 128;
+  draw_constants(seed, key_bits, p.a, p.b, &p.rng_seed);
+  *out = p;
+  return BHT_OK;
+}
+
+bht_status bht_build_retry(bht_table* t, const void* d_keys, const void* d_values, uint64_t n,
+                           uint64_t seed, uint32_t max_attempts, uint32_t* attempts_out,
+                           void* stream) {
+  if (attempts_out) *attempts_out = 0;
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  if (max_attempts == 0) return fail(BHT_ERR_INVALID_ARG, "max_attempts must be at least 1");
+  bht_status s = BHT_ERR_BUILD_FAILED;
+  for (uint32_t attempt = 0; attempt < max_attempts; ++attempt) {
+    if (attempt > 0) {
+      // new constants for every retry; everything else stays as configured
+      bht_params p = t->params;
+      draw_constants(seed + attempt - 1, t->key_bits, p.a, p.b, &p.rng_seed);
+      t->params = p;
+      t->built = false;
+    }
+    s = t->key_bits == 64
+            ? bht_build64(t, static_cast<const uint64_t*>(d_keys),
+                          static_cast<const uint64_t*>(d_values), n, stream)
+            : bht_build(t, static_cast<const uint32_t*>(d_keys),
+                        static_cast<const uint32_t*>(d_values), n, stream);
+    if (attempts_out) *attempts_out = attempt + 1;
+    if (s != BHT_ERR_BUILD_FAILED) return s;
+  }
+  return s;
 }
 
 bht_status bht_build_counted(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,

@@ -104,3 +104,68 @@ def test_create_rejects_bad_parameters_before_touching_the_device():
         with pytest.raises(bht.BhtError) as e:
             bht.bht_create(1000, bsz, scheme, p)
         assert e.value.status in (bht.BHT_ERR_INVALID_ARG, bht.BHT_ERR_UNSUPPORTED), (scheme, bsz, kw)
+
+
+def _splitmix64(state):
+    """Steele, Lea and Flood's splitmix64 step on a Python integer state."""
+    state = (state + 0x9E3779B97F4A7C15) & (2**64 - 1)
+    z = state
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & (2**64 - 1)
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & (2**64 - 1)
+    return state, z ^ (z >> 31)
+
+
+def test_splitmix64_reference_value():
+    # first output of splitmix64 from state 0, as published with the generator
+    assert _splitmix64(0)[1] == 0xE220A8397B1DCDAF
+
+
+def test_params_from_seed_draws_in_range_and_is_deterministic():
+    import paper_2108_07232_amd as bht
+    P32, P61 = 4294967291, (1 << 61) - 1
+    seen = set()
+    for seed in range(200):
+        for scheme, h in (("bcht", 3), ("bp2ht", 2), ("iht", 3), ("cht1", 3)):
+            for bits, prime in ((32, P32), (64, P61)):
+                p = bht.bht_params_from_seed(seed, scheme, bits)
+                assert p.num_hashes == h and p.key_bits == bits and p.max_chain == 128
+                assert p.rng_seed != 0 and p.iht_secondary_b == 0
+                for i in range(4):
+                    assert 1 <= p.a[i] < prime and 0 <= p.b[i] < prime
+                q = bht.bht_params_from_seed(seed, scheme, bits)
+                assert list(p.a) == list(q.a) and list(p.b) == list(q.b)
+                seen.add((bits, p.a[0]))
+    assert len(seen) == 400                 # distinct seeds give distinct constants
+    with pytest.raises(bht.BhtError):
+        bht.bht_params_from_seed(1, "bcht", 16)
+
+
+def test_params_from_seed_follows_rejection_from_splitmix64():
+    """The constants are the accepted draws of the documented stream:
+    32-bit draws (top half) for p = 2^32 - 5, 61-bit draws for 2^61 - 1."""
+    import paper_2108_07232_amd as bht
+    for bits, prime, shift in ((32, 4294967291, 32), (64, (1 << 61) - 1, 3)):
+        for seed in (0, 1, 12345, 2**64 - 1):
+            st = seed ^ 0x5EEDC0457A27
+            a, c = [], []
+            for _ in range(4):
+                while True:
+                    st, x = _splitmix64(st)
+                    x >>= shift
+                    if 1 <= x < prime:
+                        break
+                a.append(x)
+                while True:
+                    st, x = _splitmix64(st)
+                    x >>= shift
+                    if x < prime:
+                        break
+                c.append(x)
+            p = bht.bht_params_from_seed(seed, "bcht", bits)
+            assert list(p.a) == a and list(p.b) == c
+
+
+def test_build_retry_rejects_bad_arguments_on_the_host():
+    import paper_2108_07232_amd as bht
+    st = bht._lib.bht_build_retry(None, None, None, 0, 0, 1, None, None)
+    assert st == bht.BHT_ERR_INVALID_ARG

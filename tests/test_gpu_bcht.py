@@ -227,3 +227,41 @@ def test_build_probe_counts_near_paper():
     # Section VII-A: 1.11 bucket reads per insertion at b = 16, LF 0.9
     assert 1.0 <= per_key <= 1.25, per_key
     t.close()
+
+
+# ------------------------------------------------ build with reseeding
+
+def test_build_retry_recovers_from_constants_that_cannot_build():
+    """Three equal hash functions give every key a single bucket, so at load
+    factor 0.9 some bucket overflows and the first build fails; the retry
+    draws new constants (Section VII) and the rebuilt table is valid."""
+    B = bht()
+    n, seed = 20000, 99
+    keys, vals = workload(n, 77)
+    cap = datagen.capacity_for(n, 0.9)
+    t = B.Table(cap, 16, "bcht", [5, 5, 5], [7, 7, 7])
+    st, attempts = B.bht_build_retry(t.handle, dev(keys), dev(vals), seed, max_attempts=10)
+    assert st == B.BHT_OK and attempts >= 2
+    drawn = B.bht_params_from_seed(seed + attempts - 2, "bcht")
+    m = t.info[0]
+    params = oracle.Params(scheme="bcht", b=16, m=m, h=3, a=list(drawn.a)[:3],
+                           c=list(drawn.b)[:3], rng_seed=drawn.rng_seed)
+    code, msg = oracle.check32(params, t.download(), keys, vals)
+    assert code == 0, msg
+    q = datagen.mixed_queries(n, 3 * n, 0.5, 5)
+    assert_find_matches_bruteforce(t, keys, vals, q)
+    t.close()
+
+
+def test_build_retry_gives_up_after_max_attempts():
+    """With no evictions allowed a build at load factor 0.95 always meets a
+    full bucket and fails: every attempt runs and the failure is reported."""
+    B = bht()
+    n = 20000
+    keys, vals = workload(n, 78)
+    cap = datagen.capacity_for(n, 0.95)
+    a, c = datagen.hash_constants(3, 3)
+    t = B.Table(cap, 16, "bcht", a, c, max_chain=0)
+    st, attempts = B.bht_build_retry(t.handle, dev(keys), dev(vals), 5, max_attempts=3)
+    assert st == B.BHT_ERR_BUILD_FAILED and attempts == 3
+    t.close()
