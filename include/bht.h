@@ -185,12 +185,28 @@ bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint6
  * BHT_FIND_REFILL (a lane that finishes a query takes the next one) or
  * BHT_FIND_CHUNK (a wave answers 64 consecutive queries per chunk and writes
  * their results together).  grid_blocks: blocks of 256 threads per launch,
- * 0 = as many as the device keeps resident. */
+ * 0 = as many as the device keeps resident.  build_mode (BCHT and CHT1):
+ * BHT_BUILD_CONCURRENT inserts every pair with the concurrent cuckoo
+ * kernel (Section V-B); BHT_BUILD_PARTITIONED first groups the pairs by the
+ * region of their first bucket (two streaming radix passes), places each
+ * region's pairs in their first bucket in on-chip memory, writes the
+ * buckets whole, and runs the cuckoo kernel only on the pairs whose first
+ * bucket was full: the serial algorithm of Section III-A in one particular
+ * insertion order, so layouts obey the same invariants.  It allocates a
+ * library-owned workspace of about 8 bytes per pair on first use (kept
+ * until bht_destroy).  BHT_BUILD_AUTO partitions builds of at least 2^20
+ * pairs into tables whose memory the library owns (bht_create). */
 typedef enum { BHT_FIND_DEFAULT = 0, BHT_FIND_REFILL = 1, BHT_FIND_CHUNK = 2 } bht_find_schedule;
+typedef enum {
+  BHT_BUILD_AUTO = 0,
+  BHT_BUILD_CONCURRENT = 1,
+  BHT_BUILD_PARTITIONED = 2
+} bht_build_mode;
 typedef struct {
   uint32_t tile_width;
   uint32_t find_schedule;
   uint32_t grid_blocks;
+  uint32_t build_mode;
 } bht_tuning;
 bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning);
 bht_status bht_get_tuning(const bht_table* t, bht_tuning* tuning);

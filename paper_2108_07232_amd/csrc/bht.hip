@@ -17,6 +17,7 @@
 #include "bht_schemes.hpp"
 #include "bht_wide.hpp"
 #include "bht_batch.hpp"
+#include "bht_partition.hpp"
 
 using namespace bht;
 
@@ -43,6 +44,9 @@ struct bht_table {
   bool timing;             // record events around the main kernels
   hipEvent_t ev[4];        // build start/stop, find start/stop
   bool build_timed, find_timed;
+  uint32_t build_mode;     // bht_build_mode
+  void* d_part;            // partitioned build workspace (library-owned)
+  uint64_t part_bytes;
 };
 
 struct bht_batch {
@@ -319,6 +323,213 @@ Hash32 secondary_hash(const bht_table* t) {
   return make_hash32(t->params, m2, t->params.num_hashes);
 }
 
+// ------------------------------------------------- partitioned build
+
+// Smallest build that takes the partitioned path by default: below it the
+// fixed cost of its eight launches outweighs the saved atomics.
+constexpr uint64_t kPartMinKeys = 1ull << 20;
+
+struct PartKernels {
+  const void* place;
+  const void* overflow;
+};
+
+bool part_kernels(uint32_t b, uint32_t w, PartKernels* k) {
+#define BHT_PCASE(B_, W_)                                                          \
+  if (b == B_ && w == W_) {                                                        \
+    *k = {(const void*)bin_place_kernel<B_>, (const void*)overflow_build_kernel<B_, W_>}; \
+    return true;                                                                   \
+  }
+  BHT_PCASE(1, 1)
+  BHT_PCASE(4, 4)
+  BHT_PCASE(8, 4)
+  BHT_PCASE(8, 8)
+  BHT_PCASE(16, 4)
+  BHT_PCASE(16, 8)
+  BHT_PCASE(16, 16)
+  BHT_PCASE(32, 8)
+  BHT_PCASE(32, 16)
+#undef BHT_PCASE
+  return false;
+}
+
+uint32_t log2_exact(uint64_t x) {
+  uint32_t r = 0;
+  while ((1ull << r) < x) ++r;
+  return r;
+}
+
+// Bins, passes and digit counts for n pairs; false if the table has more
+// bins than two passes can address.
+bool part_plan(const bht_table* t, PartPlan* P) {
+  const uint64_t S = t->b == 1 ? bin_slots<1>() : bin_slots<16>();
+  const uint64_t R = S / t->b;
+  const uint64_t nbins = (t->m + R - 1) / R;
+  P->H = make_hash32(t->params, t->m, t->params.num_hashes);
+  P->bin_shift = log2_exact(R);
+  P->nbins = (uint32_t)nbins;
+  if (nbins <= kMaxFan) {
+    P->levels = 1;
+    P->fan1 = (uint32_t)nbins;
+  } else {
+    P->levels = 2;
+    const uint64_t fan1 = (nbins + kFan2 - 1) / kFan2;
+    if (fan1 > kMaxFan) return false;
+    P->fan1 = (uint32_t)fan1;
+  }
+  return true;
+}
+
+// Workspace carve-up (256-byte aligned pieces) for n pairs under plan P.
+struct PartLayout {
+  uint64_t hist1, hist2, total1, cursor1, seg_start, seg_len, chunk_first, total2, cursor2,
+      bin_start, bin_len, ovf_len, head, keys, vals, bytes;
+  uint64_t chunks1, chunks2;
+};
+
+PartLayout part_layout(const PartPlan& P, uint64_t n) {
+  PartLayout L{};
+  uint64_t off = 0;
+  auto take = [&off](uint64_t bytes) {
+    const uint64_t at = off;
+    off += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  L.chunks1 = (n + kPartChunk - 1) / kPartChunk;
+  L.chunks2 = P.levels == 2 ? n / kPartChunk + P.fan1 : 0;
+  L.hist1 = take(L.chunks1 * P.fan1 * 4);
+  L.hist2 = take(L.chunks2 * kFan2 * 4);
+  L.total1 = take(P.fan1 * 8ull);
+  L.cursor1 = take(P.fan1 * 8ull);
+  L.seg_start = take(P.fan1 * 8ull);
+  L.seg_len = take(P.fan1 * 8ull);
+  L.chunk_first = take((P.fan1 + 1) * 4ull);
+  L.total2 = take(P.levels == 2 ? P.fan1 * (uint64_t)kFan2 * 8 : 0);
+  L.cursor2 = take(P.levels == 2 ? P.fan1 * (uint64_t)kFan2 * 8 : 0);
+  L.bin_start = take(P.nbins * 8ull);
+  L.bin_len = take(P.nbins * 8ull);
+  L.ovf_len = take(P.nbins * 4ull);
+  L.head = take(4);
+  L.keys = take(n * 4);
+  L.vals = take(n * 4);
+  L.bytes = off;
+  return L;
+}
+
+bool use_partitioned(const bht_table* t, uint64_t n, bool counting) {
+  if (counting || n == 0) return false;
+  if (t->scheme != BHT_BCHT && t->scheme != BHT_CHT1) return false;
+  if (t->build_mode == BHT_BUILD_CONCURRENT) return false;
+  PartPlan P;
+  if (!part_plan(t, &P)) return false;
+  if (t->build_mode == BHT_BUILD_PARTITIONED) return true;
+  return n >= kPartMinKeys && t->owns_memory;
+}
+
+bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_t* vals,
+                               uint64_t n, hipStream_t st) {
+  PartPlan P;
+  if (!part_plan(t, &P)) return fail(BHT_ERR_UNSUPPORTED, "table too large to partition");
+  PartKernels K;
+  if (!part_kernels(t->b, t->tile, &K))
+    return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
+  const PartLayout L = part_layout(P, n);
+  if (t->part_bytes < L.bytes) {
+    // grow the workspace; the stream's earlier work may still use the old one
+    if (t->d_part) {
+      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(hipFree(t->d_part));
+      t->d_part = nullptr;
+      t->part_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&t->d_part, L.bytes);
+    if (e != hipSuccess) {
+      t->d_part = nullptr;
+      return fail(BHT_ERR_OOM, std::string("build workspace: ") + hipGetErrorString(e));
+    }
+    t->part_bytes = L.bytes;
+  }
+  char* w = static_cast<char*>(t->d_part);
+  PartMeta M;
+  M.hist1 = reinterpret_cast<uint32_t*>(w + L.hist1);
+  M.hist2 = reinterpret_cast<uint32_t*>(w + L.hist2);
+  M.total1 = reinterpret_cast<unsigned long long*>(w + L.total1);
+  M.cursor1 = reinterpret_cast<unsigned long long*>(w + L.cursor1);
+  M.seg_start = reinterpret_cast<unsigned long long*>(w + L.seg_start);
+  M.seg_len = reinterpret_cast<unsigned long long*>(w + L.seg_len);
+  M.chunk_first = reinterpret_cast<uint32_t*>(w + L.chunk_first);
+  M.total2 = reinterpret_cast<unsigned long long*>(w + L.total2);
+  M.cursor2 = reinterpret_cast<unsigned long long*>(w + L.cursor2);
+  M.bin_start = reinterpret_cast<unsigned long long*>(w + L.bin_start);
+  M.bin_len = reinterpret_cast<unsigned long long*>(w + L.bin_len);
+  M.ovf_len = reinterpret_cast<uint32_t*>(w + L.ovf_len);
+  M.head = reinterpret_cast<unsigned int*>(w + L.head);
+  uint32_t* keys2 = reinterpret_cast<uint32_t*>(w + L.keys);
+  uint32_t* vals2 = reinterpret_cast<uint32_t*>(w + L.vals);
+  // With two passes the first pass writes into the table's slot array,
+  // which holds at least n pairs and is rewritten whole by the placement.
+  uint32_t* mid_k = reinterpret_cast<uint32_t*>(t->d_slots);
+  uint32_t* mid_v = mid_k + n;
+
+  if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
+  part_clear_kernel<<<64, kPartBlock, 0, st>>>(M, P.fan1, P.levels, t->d_status);
+  PartPass p1;
+  p1.in_k = keys;
+  p1.in_v = vals;
+  p1.out_k = P.levels == 1 ? keys2 : mid_k;
+  p1.out_v = P.levels == 1 ? vals2 : mid_v;
+  p1.n = n;
+  p1.level = 1;
+  p1.fan = P.fan1;
+  p1.status = t->d_status;
+  p1.P = P;
+  p1.M = M;
+  part_hist_kernel<<<(unsigned)L.chunks1, kPartBlock, 0, st>>>(p1);
+  part_scan1_kernel<<<1, kPartBlock, 0, st>>>(P, M);
+  part_scatter_kernel<<<(unsigned)L.chunks1, kPartBlock, 0, st>>>(p1);
+  if (P.levels == 2) {
+    PartPass p2 = p1;
+    p2.in_k = mid_k;
+    p2.in_v = mid_v;
+    p2.out_k = keys2;
+    p2.out_v = vals2;
+    p2.level = 2;
+    p2.fan = kFan2;
+    part_hist_kernel<<<(unsigned)L.chunks2, kPartBlock, 0, st>>>(p2);
+    part_scan2_kernel<<<P.fan1, kPartBlock, 0, st>>>(P, M);
+    part_scatter_kernel<<<(unsigned)L.chunks2, kPartBlock, 0, st>>>(p2);
+  }
+  BinArgs ba;
+  ba.slots = t->d_slots;
+  ba.keys = keys2;
+  ba.vals = vals2;
+  ba.P = P;
+  ba.M = M;
+  reinterpret_cast<void (*)(BinArgs)>(const_cast<void*>(K.place))
+      <<<P.nbins, kBinBlock, 0, st>>>(ba);
+  OverflowArgs oa;
+  oa.g.slots = t->d_slots;
+  oa.g.keys = keys2;
+  oa.g.vals = vals2;
+  oa.g.n = n;
+  oa.g.status = t->d_status;
+  oa.g.probe_total = nullptr;
+  oa.g.H = P.H;
+  oa.g.max_chain = t->params.max_chain;
+  oa.g.rng_seed = t->params.rng_seed;
+  oa.M = M;
+  oa.nbins = P.nbins;
+  const int og = grid_for(K.overflow, (uint64_t)P.nbins * 64, t->grid_blocks);
+  reinterpret_cast<void (*)(OverflowArgs)>(const_cast<void*>(K.overflow))
+      <<<og, kBlock, 0, st>>>(oa);
+  HIP_TRY(hipGetLastError());
+  if (t->timing) HIP_TRY(hipEventRecord(t->ev[1], st));
+  t->build_timed = t->timing;
+  t->pending = true;
+  t->pending_n = n;
+  return BHT_OK;
+}
+
 bht_status build32_enqueue(bht_table* t, const uint32_t* keys, const uint32_t* vals, uint64_t n,
                            unsigned long long* probe_total, void* stream) {
   if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
@@ -330,6 +541,7 @@ bht_status build32_enqueue(bht_table* t, const uint32_t* keys, const uint32_t* v
     return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
   hipStream_t st = as_stream(stream);
   t->built = false;
+  if (use_partitioned(t, n, probe_total != nullptr)) return build32_partitioned(t, keys, vals, n, st);
   bht_status s = launch_fill(t, st);
   if (s != BHT_OK) return s;
   if (n) {
@@ -550,6 +762,7 @@ void bht_destroy(bht_table* t) {
   if (t->timing)
     for (int i = 0; i < 4; ++i) (void)hipEventDestroy(t->ev[i]);
   if (t->owns_memory) (void)hipFree(t->d_slots);
+  if (t->d_part) (void)hipFree(t->d_part);
   delete t;
 }
 
@@ -717,6 +930,7 @@ bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning) {
   if (!t || !tuning) return fail(BHT_ERR_INVALID_ARG, "null argument");
   const uint32_t w = tuning->tile_width ? tuning->tile_width : t->tile;
   if (tuning->find_schedule > BHT_FIND_CHUNK) return fail(BHT_ERR_INVALID_ARG, "bad schedule");
+  if (tuning->build_mode > BHT_BUILD_PARTITIONED) return fail(BHT_ERR_INVALID_ARG, "bad build mode");
   if (t->key_bits == 64) {
     if (w != 8) return fail(BHT_ERR_UNSUPPORTED, "64-bit tables read buckets with 8 lanes");
     t->grid_blocks = tuning->grid_blocks;
@@ -728,6 +942,7 @@ bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning) {
   t->tile = w;
   t->find_schedule = tuning->find_schedule;
   t->grid_blocks = tuning->grid_blocks;
+  t->build_mode = tuning->build_mode;
   return BHT_OK;
 }
 
@@ -736,6 +951,7 @@ bht_status bht_get_tuning(const bht_table* t, bht_tuning* tuning) {
   tuning->tile_width = t->tile;
   tuning->find_schedule = t->find_schedule;
   tuning->grid_blocks = t->grid_blocks;
+  tuning->build_mode = t->build_mode;
   return BHT_OK;
 }
 

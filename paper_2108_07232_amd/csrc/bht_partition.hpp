@@ -1,0 +1,423 @@
+// Partitioned bulk build of a bucketed cuckoo table (BCHT, and the
+// one-slot table).
+//
+// The paper's build inserts every pair concurrently with one bucket read
+// and one slot atomic each (Section V-B).  On MI355X the slot atomics are
+// performed at the memory side and cap such a build near 20 G pairs/s
+// whatever the load factor.  This path reaches the same kind of layout with
+// streaming traffic instead:
+//
+//   1. partition: the pairs are grouped by the region of their first
+//      bucket H_0(k) (a bin of R consecutive buckets whose slots fit in
+//      LDS), with one or two radix passes (fan-out at most 1024, then 256);
+//      each pass counts digits per chunk of 65,536 pairs, reserves output
+//      ranges per (chunk, digit), and writes each 4,096-pair sub-tile in
+//      digit order staged through LDS, so stores are contiguous runs;
+//   2. bin placement: one workgroup per bin builds its buckets in LDS,
+//      placing each pair in its first bucket at the next free slot
+//      (a local atomic on the bucket's load); pairs that find their first
+//      bucket full are kept, in place at the front of the bin's input range,
+//      as overflow; the whole bin, empty slots included, is written to the
+//      table with full-line stores (so no separate reset pass);
+//   3. overflow: the concurrent cuckoo insertion runs on the overflow pairs
+//      only, bin by bin from a device work queue.
+//
+// Steps 2 and 3 are the serial algorithm of Section III-A executed in one
+// particular order: first every pair whose first bucket still has room
+// (placement at slot = load, no eviction possible), then the remaining pairs
+// with evictions.  Any insertion order is valid for a bulk build of an
+// unordered list, so the table satisfies every layout property of the
+// concurrent build, and lookups are unchanged.  Pair order within a bin or
+// digit is not preserved and need not be.
+#pragma once
+#include "bht_kernels.hpp"
+
+namespace bht {
+
+constexpr int kPartBlock = 256;                        // threads per partition block
+constexpr int kPartSub = 4096;                         // pairs staged per sub-tile
+constexpr int kPartPer = kPartSub / kPartBlock;        // pairs per thread per sub-tile
+constexpr uint32_t kPartChunk = 16 * kPartSub;         // pairs per partition block
+constexpr uint32_t kMaxFan = 1024;                     // digits of the first pass, at most
+constexpr uint32_t kFan2 = 256;                        // digits of the second pass
+constexpr int kBinBlock = 512;                         // threads per bin placement block
+constexpr int kBinPer = 16;                            // pairs per thread per round
+
+// Slots of one bin (64 KB of LDS as 8-byte slots; the one-slot table keeps
+// a 4-byte load counter per bucket beside them, so its bins are halved).
+template <int B>
+constexpr int bin_slots() { return B == 1 ? 4096 : 8192; }
+
+struct PartPlan {
+  Hash32 H;             // first hash (index 0) and bucket count
+  uint32_t bin_shift;   // bin = H_0(k) >> bin_shift
+  uint32_t levels;      // radix passes: 1 or 2
+  uint32_t fan1;        // digits of the first pass
+  uint32_t nbins;
+};
+
+// Device metadata of one partitioned build (one allocation, see the host).
+struct PartMeta {
+  uint32_t* hist1;               // [chunks1][fan1]
+  uint32_t* hist2;               // [chunks2 bound][256]
+  unsigned long long* total1;    // [fan1]
+  unsigned long long* cursor1;   // [fan1]
+  unsigned long long* seg_start; // [fan1]  first-pass digit ranges
+  unsigned long long* seg_len;   // [fan1]
+  uint32_t* chunk_first;         // [fan1 + 1] second-pass chunks per range, prefix
+  unsigned long long* total2;    // [fan1 * 256]
+  unsigned long long* cursor2;   // [fan1 * 256]
+  unsigned long long* bin_start; // [nbins]
+  unsigned long long* bin_len;   // [nbins]
+  uint32_t* ovf_len;             // [nbins]
+  unsigned int* head;            // overflow queue head
+};
+
+// One radix pass.  Level 1 reads the caller's arrays as a single range of n
+// pairs; level 2 reads the first pass's output as fan1 ranges (seg_*).
+struct PartPass {
+  const uint32_t* in_k;
+  const uint32_t* in_v;
+  uint32_t* out_k;
+  uint32_t* out_v;
+  uint64_t n;
+  uint32_t level;
+  uint32_t fan;
+  uint32_t* status;
+  PartPlan P;
+  PartMeta M;
+};
+
+__device__ __forceinline__ uint32_t part_digit(const PartPlan& P, uint32_t level, uint32_t key) {
+  const uint32_t bin = hash32(P.H, 0, key) >> P.bin_shift;
+  if (P.levels == 1) return bin;
+  return level == 1 ? bin >> 8 : bin & (kFan2 - 1);
+}
+
+// Block -> (range, chunk): [*begin, *end) of the pass input; false when the
+// block has no chunk (the second pass launches an upper bound of blocks).
+__device__ __forceinline__ bool part_chunk(const PartPass& p, uint32_t blk, uint32_t* seg,
+                                           uint64_t* begin, uint64_t* end) {
+  if (p.level == 1) {
+    const uint64_t b = (uint64_t)blk * kPartChunk;
+    if (b >= p.n) return false;
+    *seg = 0;
+    *begin = b;
+    *end = b + kPartChunk < p.n ? b + kPartChunk : p.n;
+    return true;
+  }
+  const uint32_t* cf = p.M.chunk_first;
+  if (blk >= cf[p.P.fan1]) return false;
+  uint32_t lo = 0, hi = p.P.fan1;          // cf[lo] <= blk < cf[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (cf[mid] <= blk) lo = mid;
+    else hi = mid;
+  }
+  const uint64_t s0 = p.M.seg_start[lo], s1 = s0 + p.M.seg_len[lo];
+  const uint64_t b = s0 + (uint64_t)(blk - cf[lo]) * kPartChunk;
+  *seg = lo;
+  *begin = b;
+  *end = b + kPartChunk < s1 ? b + kPartChunk : s1;
+  return true;
+}
+
+// Exclusive prefix sums of v[0, count) into out[], count <= 4 * NT; returns
+// the total.  Every thread of the block must call it.  wt: NT / 64 words of
+// LDS.
+template <int NT, typename T, typename PI, typename PO>
+__device__ __forceinline__ T block_exclusive_scan(PI v, PO out, uint32_t count, T* wt) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  T x[4];
+  T s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t idx = tid * 4 + j;
+    x[j] = idx < count ? (T)v[idx] : (T)0;
+    s += x[j];
+  }
+  T inc = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T y = __shfl_up(inc, off, 64);
+    if (lane >= (uint32_t)off) inc += y;
+  }
+  if (lane == 63) wt[wave] = inc;
+  __syncthreads();
+  T before = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const T t = wt[w];
+    if ((uint32_t)w < wave) before += t;
+    total += t;
+  }
+  T run = before + inc - s;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t idx = tid * 4 + j;
+    if (idx < count) out[idx] = run;
+    run += x[j];
+  }
+  __syncthreads();
+  return total;
+}
+
+// Clears the counters a build accumulates into and the build status.
+__global__ void part_clear_kernel(PartMeta M, uint32_t fan1, uint32_t levels,
+                                  uint32_t* __restrict__ status) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t j = i; j < fan1; j += stride) M.total1[j] = 0;
+  if (levels == 2)
+    for (uint32_t j = i; j < fan1 * kFan2; j += stride) M.total2[j] = 0;
+  if (i == 0) *M.head = 0;
+  if (i < 4) status[i] = 0;
+}
+
+// Digit counts of one chunk: stored per chunk (for the scatter's
+// reservations) and added to the range's digit totals.
+__global__ __launch_bounds__(kPartBlock) void part_hist_kernel(PartPass p) {
+  __shared__ uint32_t cnt[kMaxFan];
+  uint32_t seg;
+  uint64_t begin, end;
+  if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
+  for (uint32_t d = threadIdx.x; d < p.fan; d += kPartBlock) cnt[d] = 0;
+  __syncthreads();
+  bool sentinel = false;
+  for (uint64_t base = begin; base < end; base += 4 * kPartBlock) {
+    uint32_t k[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint64_t i = base + j * kPartBlock + threadIdx.x;
+      k[j] = i < end ? p.in_k[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint64_t i = base + j * kPartBlock + threadIdx.x;
+      if (i < end) {
+        sentinel |= k[j] == kEmptyKey;
+        atomicAdd(&cnt[part_digit(p.P, p.level, k[j])], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t* h = p.level == 1 ? p.M.hist1 : p.M.hist2;
+  unsigned long long* tot = p.level == 1 ? p.M.total1 : p.M.total2 + (uint64_t)seg * kFan2;
+  for (uint32_t d = threadIdx.x; d < p.fan; d += kPartBlock) {
+    const uint32_t c = cnt[d];
+    h[(uint64_t)blockIdx.x * p.fan + d] = c;
+    if (c) atomicAdd(&tot[d], (unsigned long long)c);
+  }
+  if (p.level == 1 && sentinel) atomicOr(p.status, kFlagSentinel);
+}
+
+// First-pass totals -> output ranges.  One block.  With one pass the digits
+// are the bins; with two, the ranges of the second pass and its chunk counts.
+__global__ __launch_bounds__(kPartBlock) void part_scan1_kernel(PartPlan P, PartMeta M) {
+  __shared__ unsigned long long wt[kPartBlock / 64];
+  __shared__ unsigned long long base[kMaxFan];
+  __shared__ unsigned long long chunks[kMaxFan];
+  block_exclusive_scan<kPartBlock, unsigned long long>(M.total1, base, P.fan1, wt);
+  for (uint32_t d = threadIdx.x; d < P.fan1; d += kPartBlock) {
+    const unsigned long long c = M.total1[d];
+    M.cursor1[d] = base[d];
+    if (P.levels == 1) {
+      M.bin_start[d] = base[d];
+      M.bin_len[d] = c;
+    } else {
+      M.seg_start[d] = base[d];
+      M.seg_len[d] = c;
+      chunks[d] = (c + kPartChunk - 1) / kPartChunk;
+    }
+  }
+  if (P.levels == 1) return;          // uniform
+  __syncthreads();
+  const unsigned long long total =
+      block_exclusive_scan<kPartBlock, unsigned long long>(chunks, base, P.fan1, wt);
+  for (uint32_t d = threadIdx.x; d < P.fan1; d += kPartBlock) M.chunk_first[d] = (uint32_t)base[d];
+  if (threadIdx.x == 0) M.chunk_first[P.fan1] = (uint32_t)total;
+}
+
+// Second-pass totals -> bin ranges.  One block per first-pass range.
+__global__ __launch_bounds__(kPartBlock) void part_scan2_kernel(PartPlan P, PartMeta M) {
+  __shared__ unsigned long long wt[kPartBlock / 64];
+  __shared__ unsigned long long base[kFan2];
+  const uint32_t s = blockIdx.x;
+  const unsigned long long* tot = M.total2 + (uint64_t)s * kFan2;
+  block_exclusive_scan<kPartBlock, unsigned long long>(tot, base, kFan2, wt);
+  const uint32_t d = threadIdx.x;          // kPartBlock == kFan2
+  const unsigned long long pos = M.seg_start[s] + base[d];
+  M.cursor2[(uint64_t)s * kFan2 + d] = pos;
+  const uint64_t bin = (uint64_t)s * kFan2 + d;
+  if (bin < P.nbins) {
+    M.bin_start[bin] = pos;
+    M.bin_len[bin] = tot[d];
+  }
+}
+
+// Writes one chunk in digit order: reserves the chunk's range of every digit,
+// then per sub-tile ranks pairs by digit in LDS and stores each digit's run
+// contiguously.
+__global__ __launch_bounds__(kPartBlock) void part_scatter_kernel(PartPass p) {
+  __shared__ uint32_t sk[kPartSub];
+  __shared__ uint32_t sv[kPartSub];
+  __shared__ uint16_t sd[kPartSub];
+  __shared__ uint32_t cnt[kMaxFan];
+  __shared__ uint32_t start[kMaxFan];
+  __shared__ unsigned long long run[kMaxFan];
+  __shared__ uint32_t wt[kPartBlock / 64];
+  uint32_t seg;
+  uint64_t begin, end;
+  if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
+  const uint32_t* h = (p.level == 1 ? p.M.hist1 : p.M.hist2) + (uint64_t)blockIdx.x * p.fan;
+  unsigned long long* cur = p.level == 1 ? p.M.cursor1 : p.M.cursor2 + (uint64_t)seg * kFan2;
+  for (uint32_t d = threadIdx.x; d < p.fan; d += kPartBlock) {
+    const uint32_t c = h[d];
+    run[d] = c ? atomicAdd(&cur[d], (unsigned long long)c) : 0ull;
+  }
+  for (uint64_t sub = begin; sub < end; sub += kPartSub) {
+    for (uint32_t d = threadIdx.x; d < p.fan; d += kPartBlock) cnt[d] = 0;
+    __syncthreads();
+    uint32_t k[kPartPer], v[kPartPer], rank[kPartPer], dig[kPartPer];
+#pragma unroll
+    for (int j = 0; j < kPartPer; ++j) {
+      const uint64_t i = sub + j * kPartBlock + threadIdx.x;
+      k[j] = i < end ? p.in_k[i] : 0u;
+      v[j] = i < end ? p.in_v[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kPartPer; ++j) {
+      const uint64_t i = sub + j * kPartBlock + threadIdx.x;
+      if (i < end) {
+        dig[j] = part_digit(p.P, p.level, k[j]);
+        rank[j] = atomicAdd(&cnt[dig[j]], 1u);
+      }
+    }
+    __syncthreads();
+    block_exclusive_scan<kPartBlock, uint32_t>(cnt, start, p.fan, wt);
+#pragma unroll
+    for (int j = 0; j < kPartPer; ++j) {
+      const uint64_t i = sub + j * kPartBlock + threadIdx.x;
+      if (i < end) {
+        const uint32_t pos = start[dig[j]] + rank[j];
+        sk[pos] = k[j];
+        sv[pos] = v[j];
+        sd[pos] = (uint16_t)dig[j];
+      }
+    }
+    __syncthreads();
+    const uint32_t count = end - sub < (uint64_t)kPartSub ? (uint32_t)(end - sub) : kPartSub;
+    for (uint32_t i = threadIdx.x; i < count; i += kPartBlock) {
+      const uint32_t d = sd[i];
+      const uint64_t dst = run[d] + (i - start[d]);
+      p.out_k[dst] = sk[i];
+      p.out_v[dst] = sv[i];
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < p.fan; d += kPartBlock) run[d] += cnt[d];
+    // the next sub-tile's first barrier orders these updates before use
+  }
+}
+
+struct BinArgs {
+  uint64_t* slots;               // the table
+  uint32_t* keys;                // partitioned pairs; overflow is written back in place
+  uint32_t* vals;
+  PartPlan P;
+  PartMeta M;
+};
+
+// First-bucket placement of one bin in LDS, then the bin's buckets are
+// written to the table whole.
+template <int B>
+__global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
+  constexpr int S = bin_slots<B>();
+  constexpr int R = S / B;                       // buckets per bin
+  __shared__ u64x2 tbl2[S / 2];
+  __shared__ uint32_t load[R];
+  __shared__ uint32_t ovf;
+  uint64_t* tbl = reinterpret_cast<uint64_t*>(tbl2);
+  const uint32_t bin = blockIdx.x;
+  const uint64_t first = (uint64_t)bin * R;
+  const uint32_t nb = (uint64_t)a.P.H.m - first < (uint64_t)R ? (uint32_t)(a.P.H.m - first) : R;
+  const u64x2 e2 = {kEmptyPair, kEmptyPair};
+  for (int i = threadIdx.x; i < S / 2; i += kBinBlock) tbl2[i] = e2;
+  for (int i = threadIdx.x; i < R; i += kBinBlock) load[i] = 0;
+  if (threadIdx.x == 0) ovf = 0;
+  __syncthreads();
+  const uint64_t s0 = a.M.bin_start[bin], len = a.M.bin_len[bin];
+  for (uint64_t r0 = 0; r0 < len; r0 += (uint64_t)kBinBlock * kBinPer) {
+    uint32_t k[kBinPer], v[kBinPer], opos[kBinPer];
+#pragma unroll
+    for (int j = 0; j < kBinPer; ++j) {
+      const uint64_t i = r0 + j * kBinBlock + threadIdx.x;
+      k[j] = i < len ? a.keys[s0 + i] : 0u;
+      v[j] = i < len ? a.vals[s0 + i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kBinPer; ++j) {
+      opos[j] = ~0u;
+      const uint64_t i = r0 + j * kBinBlock + threadIdx.x;
+      if (i < len) {
+        // lb < nb by construction of the partition; a pair outside the bin
+        // would still be inserted correctly through the overflow path
+        const uint32_t lb = hash32(a.P.H, 0, k[j]) - (uint32_t)first;
+        const uint32_t s = lb < nb ? atomicAdd(&load[lb], 1u) : (uint32_t)B;
+        if (s < (uint32_t)B) tbl[lb * B + s] = ((uint64_t)v[j] << 32) | k[j];
+        else opos[j] = atomicAdd(&ovf, 1u);
+      }
+    }
+    // Overflow goes to the front of the bin's range: positions below the
+    // running overflow count, all of which have been read once every thread
+    // passes this barrier.
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kBinPer; ++j) {
+      if (opos[j] != ~0u) {
+        a.keys[s0 + opos[j]] = k[j];
+        a.vals[s0 + opos[j]] = v[j];
+      }
+    }
+  }
+  __syncthreads();
+  const uint64_t words = (uint64_t)nb * B;
+  u64x2* dst2 = reinterpret_cast<u64x2*>(a.slots + first * B);
+  for (uint32_t i = threadIdx.x; i < words / 2; i += kBinBlock) dst2[i] = tbl2[i];
+  if ((words & 1) && threadIdx.x == 0) a.slots[first * B + words - 1] = tbl[words - 1];
+  if (threadIdx.x == 0) a.M.ovf_len[bin] = ovf;
+}
+
+struct OverflowArgs {
+  BuildArgs32 g;                 // keys / vals = the partitioned arrays
+  PartMeta M;
+  uint32_t nbins;
+};
+
+__device__ __forceinline__ uint32_t part_queue_pop(unsigned int* head) {
+  unsigned int v = 0;
+  if (__lane_id() == 0) v = atomicAdd(head, 1u);
+  return (uint32_t)__builtin_amdgcn_readfirstlane(v);
+}
+
+// Cuckoo insertion (Section III-A) of every bin's overflow pairs; waves take
+// bins from a queue.
+template <int B, int W>
+__global__ __launch_bounds__(kBlock) void overflow_build_kernel(OverflowArgs a) {
+  const uint32_t salt = lane_salt();
+  uint32_t flags = 0;
+  for (;;) {
+    const uint32_t bin = part_queue_pop(a.M.head);
+    if (bin >= a.nbins) break;
+    const uint32_t len = a.M.ovf_len[bin];
+    if (len == 0) continue;
+    Range r;
+    r.cursor = a.M.bin_start[bin];
+    r.end = r.cursor + len;
+    uint32_t probes = 0;
+    flags |= cuckoo_build_range<B, W, false>(a.g, r, a.g.rng_seed ^ salt ^ (bin * 0x85EBCA6Bu),
+                                             &probes);
+  }
+  if (flags) atomicOr(a.g.status, flags);
+}
+
+}  // namespace bht

@@ -1,0 +1,170 @@
+"""GPU parity of the partitioned build (radix passes by first-bucket region,
+first-bucket placement in on-chip memory, cuckoo insertion of the rest).
+
+The layout it produces is the serial cuckoo algorithm's for one insertion
+order, so it is judged like every GPU layout: the oracle's invariant checker
+(each pair stored once, in a candidate bucket, occupied slots a prefix,
+early-exit property) and lookups equal to brute force, bit for bit."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests._util import dev, host_u32, host_u8, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def bht():
+    import paper_2108_07232_amd
+    return paper_2108_07232_amd
+
+
+def build_partitioned(params, keys, vals, mode="partitioned", tile=None):
+    B = bht()
+    t = B.Table(params.m * params.b, params.b, params.scheme, params.a, params.c,
+                rng_seed=params.rng_seed, max_chain=params.max_chain, tile=tile,
+                build_mode=mode)
+    st = t.build(dev(keys), dev(vals))
+    return t, st
+
+
+def check_table(t, params, keys, vals, n_queries=None, seed=3):
+    import torch
+    code, msg = oracle.check32(params, t.download(), keys, vals)
+    assert code == 0, msg
+    n = len(keys)
+    q = datagen.mixed_queries(n, n_queries or 2 * n, 0.5, seed)
+    v, f = t.find(dev(q))
+    torch.cuda.synchronize()
+    ev, ef = oracle.brute_find32(keys, vals, q)
+    np.testing.assert_array_equal(host_u8(f), ef)
+    np.testing.assert_array_equal(host_u32(v), ev)
+
+
+def plan_levels(m, b):
+    """Radix passes the library plans for m buckets of b slots."""
+    r = (4096 if b == 1 else 8192) // b
+    nbins = -(-m // r)
+    return 1 if nbins <= 1024 else 2
+
+
+@pytest.mark.parametrize("scheme,b,tile,n,lf", [
+    ("bcht", 16, 8, 1 << 20, 0.9),        # one pass, 143 bins
+    ("bcht", 16, 8, 100003, 0.95),        # ragged last bin
+    ("bcht", 16, 4, 50000, 0.98),         # heavy overflow
+    ("bcht", 16, 16, 3000, 0.9),          # a single bin
+    ("bcht", 8, 8, 300007, 0.9),
+    ("bcht", 8, 4, 1 << 18, 0.85),
+    ("bcht", 32, 16, 400009, 0.95),
+    ("bcht", 32, 8, 1 << 17, 0.9),
+    ("bcht", 4, 4, 200003, 0.8),
+    ("cht1", 1, 1, 300000, 0.8),
+])
+def test_partitioned_build_invariants_and_find(scheme, b, tile, n, lf):
+    print("partitioned %s b=%d tile=%d n=%d lf=%g" % (scheme, b, tile, n, lf), flush=True)
+    keys, vals = workload(n, 11)
+    for s in range(6):
+        params = oracle.params_for(scheme, n, lf, 500 + s, b=b)
+        t, st = build_partitioned(params, keys, vals, tile=tile)
+        if st == bht().BHT_OK:
+            break
+        assert st == bht().BHT_ERR_BUILD_FAILED
+        t.close()
+    else:
+        pytest.fail("no partitioned build succeeded")
+    assert plan_levels(params.m, b) == 1
+    check_table(t, params, keys, vals)
+    t.close()
+
+
+@pytest.mark.parametrize("scheme,b,n,lf", [
+    ("bcht", 16, 9_000_011, 0.9),         # two passes: 1,221 bins of 512 buckets
+    ("bcht", 32, 8_000_000, 0.9),
+    ("cht1", 1, 4_000_037, 0.8),          # two passes: 1,221 bins of 4,096 slots
+])
+def test_partitioned_build_two_passes(scheme, b, n, lf):
+    print("partitioned two-pass %s b=%d n=%d lf=%g" % (scheme, b, n, lf), flush=True)
+    keys, vals = workload(n, 12)
+    params = oracle.params_for(scheme, n, lf, 600, b=b)
+    assert plan_levels(params.m, b) == 2
+    t, st = build_partitioned(params, keys, vals)
+    assert st == bht().BHT_OK, bht().bht_status_string(st)
+    check_table(t, params, keys, vals, n_queries=1 << 21)
+    t.close()
+
+
+def test_build_modes_give_valid_layouts_and_identical_lookups():
+    """Default, concurrent and partitioned builds of 2^21 pairs: every layout
+    is valid and every lookup result is the same."""
+    import torch
+    n = 1 << 21
+    keys, vals = workload(n, 13)
+    params = oracle.params_for("bcht", n, 0.9, 700)
+    q = datagen.mixed_queries(n, n, 0.5, 9)
+    results = []
+    for mode in ("auto", "concurrent", "partitioned"):
+        t, st = build_partitioned(params, keys, vals, mode=mode)
+        assert st == bht().BHT_OK
+        assert oracle.check32(params, t.download(), keys, vals)[0] == 0
+        v, f = t.find(dev(q))
+        torch.cuda.synchronize()
+        results.append((host_u32(v), host_u8(f)))
+        t.close()
+    for v, f in results[1:]:
+        np.testing.assert_array_equal(v, results[0][0])
+        np.testing.assert_array_equal(f, results[0][1])
+
+
+def test_bin_with_more_pairs_than_one_placement_round():
+    """All pairs share their first bucket (H_0 = identity mod m on multiples of
+    m): one bin receives 20,000 pairs (three rounds of 8,192), 16 are placed
+    and the rest go through eviction to their other buckets."""
+    n = 20000
+    m = 12500                                    # 200,000 slots, load 0.1
+    keys = (np.arange(n, dtype=np.uint64) * m).astype(np.uint32)
+    assert len(np.unique(keys)) == n and int(keys.max()) < 4294967291
+    vals = datagen.values(n, 14)
+    _, c = datagen.hash_constants(14, 3)
+    a = [1] + list(datagen.hash_constants(15, 3)[0][1:])
+    c = [0] + list(c[1:])
+    params = oracle.Params(scheme="bcht", b=16, m=m, h=3, a=a, c=c)
+    t, st = build_partitioned(params, keys, vals)
+    assert st == bht().BHT_OK, bht().bht_status_string(st)
+    check_table(t, params, keys, vals)
+    t.close()
+
+
+def test_repeated_builds_reuse_the_workspace():
+    """Rebuilding a table (larger, then smaller inputs) gives a fresh valid
+    layout each time."""
+    B = bht()
+    params = oracle.params_for("bcht", 1 << 20, 0.9, 800)
+    t = B.Table(params.m * params.b, 16, "bcht", params.a, params.c, rng_seed=params.rng_seed,
+                build_mode="partitioned")
+    for n, seed in ((1 << 19, 21), (1 << 20, 22), (77777, 23)):
+        keys, vals = workload(n, seed)
+        assert t.build(dev(keys), dev(vals)) == B.BHT_OK
+        check_table(t, params, keys, vals, n_queries=n)
+    t.close()
+
+
+def test_partitioned_status_paths():
+    B = bht()
+    n = 1 << 16
+    keys, vals = workload(n, 24)
+    params = oracle.params_for("bcht", n, 0.9, 900)
+    bad = keys.copy()
+    bad[n // 3] = 0xFFFFFFFF
+    t, st = build_partitioned(params, bad, vals)
+    assert st == B.BHT_ERR_SENTINEL_KEY
+    t.close()
+    # one hash for all three choices: overflow can never leave its bucket
+    same = oracle.Params(scheme="bcht", b=16, m=params.m, h=3, a=[7, 7, 7], c=[9, 9, 9])
+    t, st = build_partitioned(same, keys, vals)
+    assert st == B.BHT_ERR_BUILD_FAILED
+    # the failed table rebuilds with proper constants
+    B.bht_reseed(t.handle, B.make_params(params.a, params.c))
+    assert t.build(dev(keys), dev(vals)) == B.BHT_OK
+    check_table(t, params, keys, vals, n_queries=n)
+    t.close()
