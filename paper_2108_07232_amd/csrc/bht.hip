@@ -484,9 +484,9 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
   p1.status = t->d_status;
   p1.P = P;
   p1.M = M;
-  part_hist_kernel<<<(unsigned)L.chunks1, kPartBlock, 0, st>>>(p1);
+  part_hist_kernel<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
   part_scan1_kernel<<<1, kPartBlock, 0, st>>>(P, M);
-  part_scatter_kernel<<<(unsigned)L.chunks1, kPartBlock, 0, st>>>(p1);
+  part_scatter_kernel<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
   if (P.levels == 2) {
     PartPass p2 = p1;
     p2.in_k = mid_k;
@@ -495,14 +495,17 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
     p2.out_v = vals2;
     p2.level = 2;
     p2.fan = kFan2;
-    part_hist_kernel<<<(unsigned)L.chunks2, kPartBlock, 0, st>>>(p2);
+    part_hist_kernel<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
     part_scan2_kernel<<<P.fan1, kPartBlock, 0, st>>>(P, M);
-    part_scatter_kernel<<<(unsigned)L.chunks2, kPartBlock, 0, st>>>(p2);
+    part_scatter_kernel<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
   }
   BinArgs ba;
   ba.slots = t->d_slots;
   ba.keys = keys2;
   ba.vals = vals2;
+  ba.status = t->d_status;
+  ba.max_chain = t->params.max_chain;
+  ba.rng_seed = t->params.rng_seed;
   ba.P = P;
   ba.M = M;
   reinterpret_cast<void (*)(BinArgs)>(const_cast<void*>(K.place))

@@ -319,8 +319,11 @@ enum : uint32_t { kRead = 0, kWalk = 1, kEvict = 2 };
 
 // Bucketed cuckoo insertion (Section III-A, Section V-B) of the pairs in
 // range r by the calling wave.  Returns the status flags this lane raised;
-// *probes accumulates the lane's bucket reads when COUNT.
-template <int B, int W, bool COUNT>
+// *probes accumulates the lane's bucket reads when COUNT.  EVICTED: every
+// pair of the range was just evicted from its first bucket (one exchange
+// already made), so it continues at the next bucket of the cuckoo rule with
+// one exchange counted.
+template <int B, int W, bool COUNT, bool EVICTED = false>
 __device__ __forceinline__ uint32_t cuckoo_build_range(const BuildArgs32& g, Range r,
                                                        uint32_t rng, uint32_t* probes_out) {
   const uint32_t lane = __lane_id();
@@ -352,6 +355,10 @@ __device__ __forceinline__ uint32_t cuckoo_build_range(const BuildArgs32& g, Ran
         val = v_new;
         bucket = hash32(g.H, 0, key);
         chain = 0;
+        if (EVICTED) {
+          bucket = next_bucket(g.H, key, bucket);
+          chain = 1;
+        }
         phase = kRead;
       }
     }

@@ -15,28 +15,31 @@
 //      digit order staged through LDS, so stores are contiguous runs;
 //   2. bin placement: one workgroup per bin builds its buckets in LDS,
 //      placing each pair in its first bucket at the next free slot
-//      (a local atomic on the bucket's load); pairs that find their first
-//      bucket full are kept, in place at the front of the bin's input range,
-//      as overflow; the whole bin, empty slots included, is written to the
-//      table with full-line stores (so no separate reset pass);
-//   3. overflow: the concurrent cuckoo insertion runs on the overflow pairs
-//      only, bin by bin from a device work queue.
+//      (a local atomic on the bucket's load); a pair that finds its first
+//      bucket full evicts a random resident of that bucket on chip (the
+//      first cuckoo step), and the evicted pair is kept, in place at the
+//      front of the bin's input range; the whole bin, empty slots included,
+//      is written to the table with full-line stores (so no reset pass);
+//   3. overflow: the concurrent cuckoo insertion continues every evicted
+//      pair at its next bucket, bin by bin from a device work queue.
 //
 // Steps 2 and 3 are the serial algorithm of Section III-A executed in one
 // particular order: first every pair whose first bucket still has room
-// (placement at slot = load, no eviction possible), then the remaining pairs
-// with evictions.  Any insertion order is valid for a bulk build of an
-// unordered list, so the table satisfies every layout property of the
-// concurrent build, and lookups are unchanged.  Pair order within a bin or
-// digit is not preserved and need not be.
+// (placement at slot = load), then, for each pair that meets a full first
+// bucket, the exchange with a random slot and the evicted pair's onward
+// path.  Any insertion order is valid for a bulk build of an unordered list,
+// so the table satisfies every layout property of the concurrent build, and
+// lookups are unchanged.  Pair order within a bin or digit is not preserved
+// and need not be.
 #pragma once
 #include "bht_kernels.hpp"
 
 namespace bht {
 
-constexpr int kPartBlock = 256;                        // threads per partition block
+constexpr int kPartBlock = 256;                        // threads per scan block
+constexpr int kPassBlock = 512;                        // threads per counting / scatter block
 constexpr int kPartSub = 4096;                         // pairs staged per sub-tile
-constexpr int kPartPer = kPartSub / kPartBlock;        // pairs per thread per sub-tile
+constexpr int kPartPer = kPartSub / kPassBlock;        // pairs per thread per sub-tile
 constexpr uint32_t kPartChunk = 16 * kPartSub;         // pairs per partition block
 constexpr uint32_t kMaxFan = 1024;                     // digits of the first pass, at most
 constexpr uint32_t kFan2 = 256;                        // digits of the second pass
@@ -176,24 +179,26 @@ __global__ void part_clear_kernel(PartMeta M, uint32_t fan1, uint32_t levels,
 
 // Digit counts of one chunk: stored per chunk (for the scatter's
 // reservations) and added to the range's digit totals.
-__global__ __launch_bounds__(kPartBlock) void part_hist_kernel(PartPass p) {
+__global__ __launch_bounds__(kPassBlock) void part_hist_kernel(PartPass p) {
   __shared__ uint32_t cnt[kMaxFan];
   uint32_t seg;
   uint64_t begin, end;
   if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
-  for (uint32_t d = threadIdx.x; d < p.fan; d += kPartBlock) cnt[d] = 0;
+  for (uint32_t d = threadIdx.x; d < p.fan; d += kPassBlock) cnt[d] = 0;
   __syncthreads();
   bool sentinel = false;
-  for (uint64_t base = begin; base < end; base += 4 * kPartBlock) {
-    uint32_t k[4];
+  constexpr int U = 8;
+  for (uint64_t base = begin; base < end; base += U * kPassBlock) {
+    uint32_t k[U];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint64_t i = base + j * kPartBlock + threadIdx.x;
-      k[j] = i < end ? p.in_k[i] : 0u;
+    for (int j = 0; j < U; ++j) {
+      // branch-free loads: indices past the end re-read the last pair
+      const uint64_t i = base + j * kPassBlock + threadIdx.x;
+      k[j] = p.in_k[i < end ? i : end - 1];
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint64_t i = base + j * kPartBlock + threadIdx.x;
+    for (int j = 0; j < U; ++j) {
+      const uint64_t i = base + j * kPassBlock + threadIdx.x;
       if (i < end) {
         sentinel |= k[j] == kEmptyKey;
         atomicAdd(&cnt[part_digit(p.P, p.level, k[j])], 1u);
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(kPartBlock) void part_hist_kernel(PartPass p) {
   __syncthreads();
   uint32_t* h = p.level == 1 ? p.M.hist1 : p.M.hist2;
   unsigned long long* tot = p.level == 1 ? p.M.total1 : p.M.total2 + (uint64_t)seg * kFan2;
-  for (uint32_t d = threadIdx.x; d < p.fan; d += kPartBlock) {
+  for (uint32_t d = threadIdx.x; d < p.fan; d += kPassBlock) {
     const uint32_t c = cnt[d];
     h[(uint64_t)blockIdx.x * p.fan + d] = c;
     if (c) atomicAdd(&tot[d], (unsigned long long)c);
@@ -257,47 +262,60 @@ __global__ __launch_bounds__(kPartBlock) void part_scan2_kernel(PartPlan P, Part
 
 // Writes one chunk in digit order: reserves the chunk's range of every digit,
 // then per sub-tile ranks pairs by digit in LDS and stores each digit's run
-// contiguously.
-__global__ __launch_bounds__(kPartBlock) void part_scatter_kernel(PartPass p) {
+// contiguously.  The next sub-tile's loads are issued before the current
+// one is ranked, so they overlap the on-chip work.
+__global__ __launch_bounds__(kPassBlock) void part_scatter_kernel(PartPass p) {
   __shared__ uint32_t sk[kPartSub];
   __shared__ uint32_t sv[kPartSub];
   __shared__ uint16_t sd[kPartSub];
   __shared__ uint32_t cnt[kMaxFan];
   __shared__ uint32_t start[kMaxFan];
   __shared__ unsigned long long run[kMaxFan];
-  __shared__ uint32_t wt[kPartBlock / 64];
+  __shared__ uint32_t wt[kPassBlock / 64];
   uint32_t seg;
   uint64_t begin, end;
   if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
   const uint32_t* h = (p.level == 1 ? p.M.hist1 : p.M.hist2) + (uint64_t)blockIdx.x * p.fan;
   unsigned long long* cur = p.level == 1 ? p.M.cursor1 : p.M.cursor2 + (uint64_t)seg * kFan2;
-  for (uint32_t d = threadIdx.x; d < p.fan; d += kPartBlock) {
+  for (uint32_t d = threadIdx.x; d < p.fan; d += kPassBlock) {
     const uint32_t c = h[d];
     run[d] = c ? atomicAdd(&cur[d], (unsigned long long)c) : 0ull;
   }
+  // Loads are branch-free (indices past the end re-read the last pair, and
+  // those copies are never ranked), so the compiler can leave the next
+  // sub-tile's loads in flight while the current one is ranked.
+  const uint64_t last = end - 1;
+  uint32_t k[kPartPer], v[kPartPer];
+#pragma unroll
+  for (int j = 0; j < kPartPer; ++j) {
+    const uint64_t i = begin + j * kPassBlock + threadIdx.x;
+    k[j] = p.in_k[i < end ? i : last];
+    v[j] = p.in_v[i < end ? i : last];
+  }
   for (uint64_t sub = begin; sub < end; sub += kPartSub) {
-    for (uint32_t d = threadIdx.x; d < p.fan; d += kPartBlock) cnt[d] = 0;
-    __syncthreads();
-    uint32_t k[kPartPer], v[kPartPer], rank[kPartPer], dig[kPartPer];
+    uint32_t nk[kPartPer], nv[kPartPer];
 #pragma unroll
     for (int j = 0; j < kPartPer; ++j) {
-      const uint64_t i = sub + j * kPartBlock + threadIdx.x;
-      k[j] = i < end ? p.in_k[i] : 0u;
-      v[j] = i < end ? p.in_v[i] : 0u;
+      const uint64_t i = sub + kPartSub + j * kPassBlock + threadIdx.x;
+      nk[j] = p.in_k[i < end ? i : last];
+      nv[j] = p.in_v[i < end ? i : last];
     }
+    for (uint32_t d = threadIdx.x; d < p.fan; d += kPassBlock) cnt[d] = 0;
+    __syncthreads();
+    uint32_t rank[kPartPer], dig[kPartPer];
 #pragma unroll
     for (int j = 0; j < kPartPer; ++j) {
-      const uint64_t i = sub + j * kPartBlock + threadIdx.x;
+      const uint64_t i = sub + j * kPassBlock + threadIdx.x;
       if (i < end) {
         dig[j] = part_digit(p.P, p.level, k[j]);
         rank[j] = atomicAdd(&cnt[dig[j]], 1u);
       }
     }
     __syncthreads();
-    block_exclusive_scan<kPartBlock, uint32_t>(cnt, start, p.fan, wt);
+    block_exclusive_scan<kPassBlock, uint32_t>(cnt, start, p.fan, wt);
 #pragma unroll
     for (int j = 0; j < kPartPer; ++j) {
-      const uint64_t i = sub + j * kPartBlock + threadIdx.x;
+      const uint64_t i = sub + j * kPassBlock + threadIdx.x;
       if (i < end) {
         const uint32_t pos = start[dig[j]] + rank[j];
         sk[pos] = k[j];
@@ -307,28 +325,47 @@ __global__ __launch_bounds__(kPartBlock) void part_scatter_kernel(PartPass p) {
     }
     __syncthreads();
     const uint32_t count = end - sub < (uint64_t)kPartSub ? (uint32_t)(end - sub) : kPartSub;
-    for (uint32_t i = threadIdx.x; i < count; i += kPartBlock) {
-      const uint32_t d = sd[i];
-      const uint64_t dst = run[d] + (i - start[d]);
-      p.out_k[dst] = sk[i];
-      p.out_v[dst] = sv[i];
+    // fixed trip count (no inner loop), so the prefetched loads stay in
+    // flight across the stores
+#pragma unroll
+    for (int j = 0; j < kPartPer; ++j) {
+      const uint32_t i = j * kPassBlock + threadIdx.x;
+      if (i < count) {
+        const uint32_t d = sd[i];
+        const uint64_t dst = run[d] + (i - start[d]);
+        p.out_k[dst] = sk[i];
+        p.out_v[dst] = sv[i];
+      }
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < p.fan; d += kPartBlock) run[d] += cnt[d];
+    for (uint32_t d = threadIdx.x; d < p.fan; d += kPassBlock) run[d] += cnt[d];
     // the next sub-tile's first barrier orders these updates before use
+#pragma unroll
+    for (int j = 0; j < kPartPer; ++j) {
+      k[j] = nk[j];
+      v[j] = nv[j];
+    }
   }
 }
 
 struct BinArgs {
   uint64_t* slots;               // the table
-  uint32_t* keys;                // partitioned pairs; overflow is written back in place
+  uint32_t* keys;                // partitioned pairs; evicted pairs are written back in place
   uint32_t* vals;
+  uint32_t* status;
+  uint32_t max_chain;
+  uint32_t rng_seed;
   PartPlan P;
   PartMeta M;
 };
 
-// First-bucket placement of one bin in LDS, then the bin's buckets are
-// written to the table whole.
+// One bin in LDS.  Each pair claims the next slot of its first bucket (a
+// local atomic on the bucket's load).  A pair that finds the bucket full
+// makes the cuckoo step of Section III-A on chip: after a barrier (every
+// claimed slot is then written) it exchanges itself with a random slot of
+// the bucket, and the evicted pair is written to the front of the bin's
+// input range, to continue at its next bucket in the overflow kernel.  The
+// bin's buckets, empty slots included, are then stored whole.
 template <int B>
 __global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
   constexpr int S = bin_slots<B>();
@@ -336,7 +373,7 @@ __global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
   __shared__ u64x2 tbl2[S / 2];
   __shared__ uint32_t load[R];
   __shared__ uint32_t ovf;
-  uint64_t* tbl = reinterpret_cast<uint64_t*>(tbl2);
+  unsigned long long* tbl = reinterpret_cast<unsigned long long*>(tbl2);
   const uint32_t bin = blockIdx.x;
   const uint64_t first = (uint64_t)bin * R;
   const uint32_t nb = (uint64_t)a.P.H.m - first < (uint64_t)R ? (uint32_t)(a.P.H.m - first) : R;
@@ -344,38 +381,62 @@ __global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
   for (int i = threadIdx.x; i < S / 2; i += kBinBlock) tbl2[i] = e2;
   for (int i = threadIdx.x; i < R; i += kBinBlock) load[i] = 0;
   if (threadIdx.x == 0) ovf = 0;
+  uint32_t rng = a.rng_seed ^ (bin * 0x9E3779B9u) ^ (threadIdx.x * 0x85EBCA6Bu);
+  if (rng == 0) rng = 0x2545F491u;
+  uint32_t flags = 0;
   __syncthreads();
   const uint64_t s0 = a.M.bin_start[bin], len = a.M.bin_len[bin];
   for (uint64_t r0 = 0; r0 < len; r0 += (uint64_t)kBinBlock * kBinPer) {
-    uint32_t k[kBinPer], v[kBinPer], opos[kBinPer];
+    uint32_t k[kBinPer], v[kBinPer], full[kBinPer];
 #pragma unroll
     for (int j = 0; j < kBinPer; ++j) {
+      // branch-free loads: indices past the end re-read the bin's last pair
       const uint64_t i = r0 + j * kBinBlock + threadIdx.x;
-      k[j] = i < len ? a.keys[s0 + i] : 0u;
-      v[j] = i < len ? a.vals[s0 + i] : 0u;
+      k[j] = a.keys[s0 + (i < len ? i : len - 1)];
+      v[j] = a.vals[s0 + (i < len ? i : len - 1)];
     }
 #pragma unroll
     for (int j = 0; j < kBinPer; ++j) {
-      opos[j] = ~0u;
+      full[j] = ~0u;
       const uint64_t i = r0 + j * kBinBlock + threadIdx.x;
       if (i < len) {
-        // lb < nb by construction of the partition; a pair outside the bin
-        // would still be inserted correctly through the overflow path
+        // lb < nb by construction of the partition
         const uint32_t lb = hash32(a.P.H, 0, k[j]) - (uint32_t)first;
-        const uint32_t s = lb < nb ? atomicAdd(&load[lb], 1u) : (uint32_t)B;
-        if (s < (uint32_t)B) tbl[lb * B + s] = ((uint64_t)v[j] << 32) | k[j];
-        else opos[j] = atomicAdd(&ovf, 1u);
+        if (lb >= nb) {
+          flags |= kFlagFailed;
+        } else {
+          const uint32_t s = atomicAdd(&load[lb], 1u);
+          if (s < (uint32_t)B) tbl[lb * B + s] = ((unsigned long long)v[j] << 32) | k[j];
+          else full[j] = lb;
+        }
       }
     }
-    // Overflow goes to the front of the bin's range: positions below the
-    // running overflow count, all of which have been read once every thread
-    // passes this barrier.
+    // Every claimed slot is written, and every pair of this round has been
+    // read: evicted pairs go to positions below the running eviction count.
     __syncthreads();
+    // all exchanges first, then the stores of the evicted pairs (a store
+    // between two exchanges would make each exchange wait for it)
 #pragma unroll
     for (int j = 0; j < kBinPer; ++j) {
-      if (opos[j] != ~0u) {
-        a.keys[s0 + opos[j]] = k[j];
-        a.vals[s0 + opos[j]] = v[j];
+      if (full[j] != ~0u) {
+        if (a.max_chain == 0) {
+          flags |= kFlagFailed;
+          full[j] = ~0u;
+        } else {
+          rng = xorshift32(rng);
+          const unsigned long long old = atomicExch(
+              &tbl[full[j] * B + rng % (uint32_t)B], ((unsigned long long)v[j] << 32) | k[j]);
+          full[j] = atomicAdd(&ovf, 1u);
+          k[j] = (uint32_t)old;
+          v[j] = (uint32_t)(old >> 32);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kBinPer; ++j) {
+      if (full[j] != ~0u) {
+        a.keys[s0 + full[j]] = k[j];
+        a.vals[s0 + full[j]] = v[j];
       }
     }
   }
@@ -385,6 +446,7 @@ __global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
   for (uint32_t i = threadIdx.x; i < words / 2; i += kBinBlock) dst2[i] = tbl2[i];
   if ((words & 1) && threadIdx.x == 0) a.slots[first * B + words - 1] = tbl[words - 1];
   if (threadIdx.x == 0) a.M.ovf_len[bin] = ovf;
+  if (flags) atomicOr(a.status, flags);
 }
 
 struct OverflowArgs {
@@ -399,7 +461,8 @@ __device__ __forceinline__ uint32_t part_queue_pop(unsigned int* head) {
   return (uint32_t)__builtin_amdgcn_readfirstlane(v);
 }
 
-// Cuckoo insertion (Section III-A) of every bin's overflow pairs; waves take
+// Cuckoo insertion (Section III-A) of the pairs evicted during placement,
+// each continuing at its next bucket with one exchange counted; waves take
 // bins from a queue.
 template <int B, int W>
 __global__ __launch_bounds__(kBlock) void overflow_build_kernel(OverflowArgs a) {
@@ -414,8 +477,8 @@ __global__ __launch_bounds__(kBlock) void overflow_build_kernel(OverflowArgs a) 
     r.cursor = a.M.bin_start[bin];
     r.end = r.cursor + len;
     uint32_t probes = 0;
-    flags |= cuckoo_build_range<B, W, false>(a.g, r, a.g.rng_seed ^ salt ^ (bin * 0x85EBCA6Bu),
-                                             &probes);
+    flags |= cuckoo_build_range<B, W, false, true>(
+        a.g, r, a.g.rng_seed ^ salt ^ (bin * 0x85EBCA6Bu), &probes);
   }
   if (flags) atomicOr(a.g.status, flags);
 }
