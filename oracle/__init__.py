@@ -56,6 +56,7 @@ class _Params(ctypes.Structure):
         ("rng_seed", ctypes.c_uint32),
         ("mock_n", ctypes.c_uint32),
         ("mock_hash", ctypes.POINTER(ctypes.c_uint32)),
+        ("iht_early_exit", ctypes.c_uint32),
     ]
 
 
@@ -111,6 +112,7 @@ class Params:
     m2: int = 0
     rng_seed: int = 0x9E3779B9
     mock: np.ndarray | None = None   # (mock_n, h) uint32 bucket table, tests only
+    early_exit: bool = False         # iceberg find: stop after a primary below t
     _keep: list = field(default_factory=list, repr=False)
 
     def to_c(self) -> _Params:
@@ -121,6 +123,7 @@ class Params:
             p.a[i] = int(self.a[i]) if i < len(self.a) else 0
             p.c[i] = int(self.c[i]) if i < len(self.c) else 0
         p.threshold, p.b2, p.m2, p.rng_seed = self.threshold, self.b2, self.m2, self.rng_seed
+        p.iht_early_exit = 1 if self.early_exit else 0
         if self.mock is not None:
             mk = np.ascontiguousarray(self.mock, dtype=np.uint32)
             self._keep = [mk]

@@ -309,8 +309,12 @@ static int find_in32(const uint64_t* t, bucket_ref B, uint32_t q, uint32_t* v) {
  * in order; stop on a hit, and stop with a miss after a bucket that lacks
  * the key and is not full (insertion order never skips a bucket with room).
  * Power-of-two (Section V-C) and iceberg (Section III-C, V-D): probe every
- * candidate in order until a hit, no early exit on room.  A query equal to
- * the sentinel is never a stored key and misses without probing. */
+ * candidate in order until a hit, no early exit on room.  Iceberg with
+ * iht_early_exit: a key goes to a secondary bucket only when its primary
+ * already holds at least t keys (Section III-C), and loads never decrease,
+ * so a miss in a primary that holds fewer than t keys proves absence and
+ * ends the query after one probe.  A query equal to the sentinel is never a
+ * stored key and misses without probing. */
 void orc_find32(const orc_params* p, const uint64_t* table, const uint32_t* q,
                 uint64_t nq, uint32_t* out_v, uint8_t* out_f, uint64_t* probes,
                 uint8_t* per_query_probes) {
@@ -327,6 +331,9 @@ void orc_find32(const orc_params* p, const uint64_t* table, const uint32_t* q,
           break;
         }
         if (early_exit && load32(table, B) < B.size) break;
+        if (p->scheme == ORC_IHT && p->iht_early_exit && j == 0 &&
+            load32(table, B) < p->threshold)
+          break;
       }
     }
     if (!found) v = EMPTY32;

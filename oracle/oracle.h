@@ -45,6 +45,8 @@ typedef struct {
   uint32_t rng_seed;    /* eviction-victim xorshift32 seed (nonzero)             */
   uint32_t mock_n;      /* >0: hash values come from mock_hash instead (tests)   */
   const uint32_t* mock_hash; /* mock_hash[key*h + i] = bucket of hash i, key < mock_n */
+  uint32_t iht_early_exit; /* IHT find: a miss in a primary holding fewer than    */
+                           /* threshold keys ends the query (see orc_find32)      */
 } orc_params;
 
 /* ((a*k + c) mod 4294967291) mod m, Section VII hash family. */

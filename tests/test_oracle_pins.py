@@ -513,3 +513,40 @@ def test_iceberg_probe_counts_match_paper():
         assert s["neg"] == c["negative"]["value"]
         assert abs(s["insert"] - ins) <= 0.03, (pct, s["insert"], ins)
         assert abs(s["pos"] - pos) <= 0.03, (pct, s["pos"], pos)
+
+
+@pytest.mark.parametrize("b2,t,lf,both", [(0, 13, 0.86, True), (0, 6, 0.8, False),
+                                           (8, 16, 0.8, True)])
+def test_iceberg_early_exit_find_equals_brute_force(b2, t, lf, both):
+    """Early exit after a primary below the threshold loses no key (results
+    equal the plain definition), leaves positive probe counts unchanged, and
+    cuts a negative query to one probe exactly when its primary holds fewer
+    than t keys."""
+    n = 20000
+    for seed in range(1, 8):
+        keys, vals = datagen.unique_keys(n, seed), datagen.values(n, seed)
+        params = oracle.params_for("iht", n, lf, seed, b=16, threshold=t)
+        if b2:
+            params.b2 = b2
+            params.m2 = max(1, params.m * 16 // 8 // b2)
+        st, table, _ = oracle.build32(params, keys, vals)
+        if st == oracle.OK:
+            break
+    else:
+        pytest.fail("no iceberg build succeeded")
+    q = datagen.mixed_queries(n, 2 * n, 0.5, seed)
+    _, _, _, per_plain = oracle.find32(params, table, q)
+    params.early_exit = True
+    v, f, _, per = oracle.find32(params, table, q)
+    bv, bf = oracle.brute_find32(keys, vals, q)
+    np.testing.assert_array_equal(f, bf)
+    np.testing.assert_array_equal(v, bv)
+    np.testing.assert_array_equal(per[f == 1], per_plain[f == 1])
+    prim = oracle.hash32_many(params.a[0], params.c[0], q, params.m).astype(np.int64)
+    loads = (table[:params.m * 16].reshape(-1, 16) & np.uint64(0xFFFFFFFF)) != np.uint64(0xFFFFFFFF)
+    below = loads.sum(axis=1)[prim] < t
+    neg = f == 0
+    assert np.all(per[neg & below] == 1) and np.all(per[neg & ~below] == 3)
+    assert (neg & ~below).any()
+    if both:        # a low threshold leaves (almost) no primary below it
+        assert (neg & below).any()
