@@ -60,18 +60,38 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(probes):
+def algorithmic_bytes(probes, build=None):
     """Bytes the method must move per key (Section VII-F cost model):
     a probe reads one 128-byte bucket; every insertion step ends in one slot
     atomic (a CAS or an exchange) charged one write granule; a query reads
-    its key and writes a 4-byte value and a 1-byte flag; a build reads an
-    8-byte pair."""
-    return {
+    its key and writes a 4-byte value and a 1-byte flag; a concurrent build
+    reads an 8-byte pair per key.
+
+    build: statistics of a partitioned build (passes, slots per key,
+    evicted pairs per key, overflow bucket reads per key), whose bytes are
+    its streaming passes (each radix pass counts keys, 4 B, then reads and
+    writes pairs, 16 B), the placement (reads 8 B, writes every slot of the
+    table, 8 B per slot), the evicted pairs (written and read back, 16 B
+    each) and the overflow insertion (a probe plus a slot atomic per bucket
+    read)."""
+    out = {
         "build": 8 + probes["insert"] * (128 + WRITE_GRANULE),
         "find_pos": 9 + 128 * probes["pos"],
         "find_neg": 9 + 128 * probes["neg"],
         "find_mix": 9 + 128 * probes["mix"],
     }
+    if build:
+        out["build"] = (20 * build["passes"] + 8 + 8 * build["slots_per_key"]
+                        + 16 * build["evicted_per_key"]
+                        + build["overflow_probes_per_key"] * (128 + WRITE_GRANULE))
+    return out
+
+
+def partition_passes(m, b):
+    """Radix passes the library plans for m buckets of b slots (bins of
+    8,192 slots, 4,096 for one-slot buckets; one pass up to 1,024 bins)."""
+    r = (4096 if b == 1 else 8192) // b
+    return 1 if -(-m // r) <= 1024 else 2
 
 
 def measure_ceilings(bht, table, torch, stream):
@@ -633,6 +653,13 @@ def run_lfsweep(args):
                 ms["build"].append(build_ms)
                 for k, v in find_ms.items():
                     ms[k].append(v)
+        part, evicted, ovf_probes = bht.bht_build_stats(table.handle)
+        m, b, _, table_bytes = table.info
+        build_stats = None
+        if part:
+            build_stats = {"passes": partition_passes(m, b), "slots_per_key": m * b / n,
+                           "evicted_per_key": evicted / n,
+                           "overflow_probes_per_key": ovf_probes / n}
         total = torch.zeros(1, dtype=torch.int64, device=dev)
         st = bht.bht_build_counted(table.handle, d_keys, d_vals, total)
         probes = {"insert": int(total.item()) / n if st == bht.BHT_OK else None}
@@ -640,10 +667,12 @@ def run_lfsweep(args):
         for qname in ("find_pos", "find_neg", "find_mix"):
             bht.bht_find_counted(table.handle, d_q[qname], out_v, out_f, pr, stream=stream)
             probes[qname.replace("find_", "")] = float(pr.sum(dtype=torch.int64).item()) / n
-        m, b, _, table_bytes = table.info
         entry = {"load_factor": lf, "actual_load_factor": round(n / (m * b), 6), "buckets": m,
                  "table_bytes": table_bytes, "max_chain": max_chain,
                  "build_failures": failures + timed_failures,
+                 "build_path": "partitioned" if part else "concurrent",
+                 "build_stats": ({k: round(v, 5) for k, v in build_stats.items()}
+                                 if build_stats else None),
                  "probes_per_key": {k: (round(v, 4) if v is not None else None)
                                     for k, v in probes.items()}}
         for k, v in ms.items():
@@ -651,7 +680,7 @@ def run_lfsweep(args):
             entry[k + "_ms"] = round(avg, 4)
             entry[k + "_gkeys_s"] = round(n / (avg * 1e-3) / 1e9, 4)
         if probes["insert"] is not None:
-            bytes_per = algorithmic_bytes(probes)
+            bytes_per = algorithmic_bytes(probes, build_stats)
             entry["model_gbs"] = {k: round(bytes_per[k] * n / (entry[k + "_ms"] * 1e-3) / 1e9, 1)
                                   for k in bytes_per}
         results.append(entry)
@@ -852,7 +881,12 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on 2^%d keys" % args.cpu_log2n)
         cpu, probes = cpu_baseline(args, 1 << args.cpu_log2n)
-    bytes_per = algorithmic_bytes(probes) if probes else None
+    part, evicted, ovf_probes = bht.bht_build_stats(table.handle)
+    build_stats = None
+    if part:
+        build_stats = {"passes": partition_passes(m, b), "slots_per_key": m * b / n,
+                       "evicted_per_key": evicted / n, "overflow_probes_per_key": ovf_probes / n}
+    bytes_per = algorithmic_bytes(probes, build_stats) if probes else None
 
     kernels = {}
     for name in ("build", "find_pos", "find_neg", "find_mix"):
@@ -907,6 +941,8 @@ def main():
         "cpu_baseline": cpu,
         "ceilings": ceilings,
         "probes_per_key_oracle": {k: round(v, 4) for k, v in probes.items()} if probes else None,
+        "build_path": "partitioned" if part else "concurrent",
+        "build_stats": {k: round(v, 5) for k, v in build_stats.items()} if build_stats else None,
         "build_failures": failures,
         "mixed_found": found_mix,
         "paper_context": {"hardware": "NVIDIA TITAN V", "build_gkeys_s": 1.34438,

@@ -156,6 +156,16 @@ bht_status bht_build_retry(bht_table* t, const void* d_keys, const void* d_value
                            uint64_t seed, uint32_t max_attempts, uint32_t* attempts_out,
                            void* stream);
 
+/* Statistics of the last successful 32-bit build: *partitioned = 1 if it
+ * took the partitioned path (see bht_tuning), else 0.  For a partitioned
+ * build, *evicted = pairs that met a full first bucket and evicted a
+ * resident on chip, and *overflow_probes = bucket reads made while those
+ * evicted pairs were inserted (Section VII-E's probe: one bucket read);
+ * both 0 for a concurrent build.  Returns NOT_BUILT before a successful
+ * build. */
+bht_status bht_build_stats(const bht_table* t, uint32_t* partitioned, uint64_t* evicted,
+                           uint64_t* overflow_probes);
+
 /* Bulk find of n queries (Section III; Section V).  d_out_values[i] is the
  * value stored with d_queries[i], or 0xFFFFFFFF when absent; d_out_found[i]
  * is 1 when present, else 0.  Asynchronous on stream; the table must be

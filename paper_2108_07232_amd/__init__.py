@@ -88,6 +88,7 @@ _SIGS = {
     "bht_build64": (_st, [_p, _p, _p, _u64, _p]),
     "bht_find64": (_st, [_p, _p, _u64, _p, _p, _p]),
     "bht_build_counted": (_st, [_p, _p, _p, _u64, _p, _p]),
+    "bht_build_stats": (_st, [_p, ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "bht_params_from_seed": (_st, [_u64, ctypes.c_int, _u32, ctypes.POINTER(bht_params)]),
     "bht_build_retry": (_st, [_p, _p, _p, _u64, _u64, _u32, ctypes.POINTER(_u32), _p]),
     "bht_find_counted": (_st, [_p, _p, _u64, _p, _p, _p, _p]),
@@ -249,6 +250,14 @@ def bht_find64(table, queries, out_values, out_found, n=None, stream=None):
     _check(_lib.bht_find64(table, _dptr(queries, None, "queries"), n,
                            _dptr(out_values, None, "out_values"),
                            _dptr(out_found, None, "out_found"), _stream(stream)), "bht_find64")
+
+
+def bht_build_stats(table):
+    """(partitioned, evicted pairs, overflow bucket reads) of the last build."""
+    part, ev, pr = _u32(0), _u64(0), _u64(0)
+    _check(_lib.bht_build_stats(table, ctypes.byref(part), ctypes.byref(ev), ctypes.byref(pr)),
+           "bht_build_stats")
+    return bool(part.value), ev.value, pr.value
 
 
 def bht_params_from_seed(seed: int, scheme, key_bits: int = 32) -> bht_params:

@@ -47,6 +47,10 @@ struct bht_table {
   uint32_t build_mode;     // bht_build_mode
   void* d_part;            // partitioned build workspace (library-owned)
   uint64_t part_bytes;
+  bool pending_partitioned;
+  bool last_partitioned;   // the last successful build took the partitioned path
+  uint64_t last_evicted;   // ... and evicted this many pairs on chip
+  uint64_t last_probes;    // ... and read this many buckets inserting them
 };
 
 struct bht_batch {
@@ -530,6 +534,7 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
   t->build_timed = t->timing;
   t->pending = true;
   t->pending_n = n;
+  t->pending_partitioned = true;
   return BHT_OK;
 }
 
@@ -544,6 +549,7 @@ bht_status build32_enqueue(bht_table* t, const uint32_t* keys, const uint32_t* v
     return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
   hipStream_t st = as_stream(stream);
   t->built = false;
+  t->pending_partitioned = false;
   if (use_partitioned(t, n, probe_total != nullptr)) return build32_partitioned(t, keys, vals, n, st);
   bht_status s = launch_fill(t, st);
   if (s != BHT_OK) return s;
@@ -796,6 +802,22 @@ bht_status bht_build_wait(bht_table* t, void* stream) {
   if (flags & kFlagFailed) return fail(BHT_ERR_BUILD_FAILED, "eviction cap reached");
   t->built = true;
   t->n_stored = t->pending_n;
+  t->last_partitioned = t->pending_partitioned;
+  t->last_evicted = t->pending_partitioned ? t->h_status[1] : 0;
+  t->last_probes = t->pending_partitioned
+                       ? ((uint64_t)t->h_status[3] << 32 | t->h_status[2])
+                       : 0;
+  return BHT_OK;
+}
+
+bht_status bht_build_stats(const bht_table* t, uint32_t* partitioned, uint64_t* evicted,
+                           uint64_t* overflow_probes) {
+  if (!t || !partitioned || !evicted || !overflow_probes)
+    return fail(BHT_ERR_INVALID_ARG, "null argument");
+  if (!t->built) return fail(BHT_ERR_NOT_BUILT, "no successful build");
+  *partitioned = t->last_partitioned ? 1u : 0u;
+  *evicted = t->last_evicted;
+  *overflow_probes = t->last_probes;
   return BHT_OK;
 }
 

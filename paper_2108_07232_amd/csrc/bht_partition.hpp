@@ -445,7 +445,10 @@ __global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
   u64x2* dst2 = reinterpret_cast<u64x2*>(a.slots + first * B);
   for (uint32_t i = threadIdx.x; i < words / 2; i += kBinBlock) dst2[i] = tbl2[i];
   if ((words & 1) && threadIdx.x == 0) a.slots[first * B + words - 1] = tbl[words - 1];
-  if (threadIdx.x == 0) a.M.ovf_len[bin] = ovf;
+  if (threadIdx.x == 0) {
+    a.M.ovf_len[bin] = ovf;
+    if (ovf) atomicAdd(a.status + 1, ovf);       // evicted pairs of the build
+  }
   if (flags) atomicOr(a.status, flags);
 }
 
@@ -464,10 +467,12 @@ __device__ __forceinline__ uint32_t part_queue_pop(unsigned int* head) {
 // Cuckoo insertion (Section III-A) of the pairs evicted during placement,
 // each continuing at its next bucket with one exchange counted; waves take
 // bins from a queue.
+// The bucket reads of this phase are summed into status words 2-3 (one
+// atomic per wave).
 template <int B, int W>
 __global__ __launch_bounds__(kBlock) void overflow_build_kernel(OverflowArgs a) {
   const uint32_t salt = lane_salt();
-  uint32_t flags = 0;
+  uint32_t flags = 0, probes = 0;
   for (;;) {
     const uint32_t bin = part_queue_pop(a.M.head);
     if (bin >= a.nbins) break;
@@ -476,11 +481,13 @@ __global__ __launch_bounds__(kBlock) void overflow_build_kernel(OverflowArgs a) 
     Range r;
     r.cursor = a.M.bin_start[bin];
     r.end = r.cursor + len;
-    uint32_t probes = 0;
-    flags |= cuckoo_build_range<B, W, false, true>(
+    flags |= cuckoo_build_range<B, W, true, true>(
         a.g, r, a.g.rng_seed ^ salt ^ (bin * 0x85EBCA6Bu), &probes);
   }
   if (flags) atomicOr(a.g.status, flags);
+  const uint32_t total = wave_sum(probes);
+  if (__lane_id() == 0 && total)
+    atomicAdd(reinterpret_cast<unsigned long long*>(a.g.status + 2), (unsigned long long)total);
 }
 
 }  // namespace bht

@@ -168,3 +168,36 @@ def test_partitioned_status_paths():
     assert t.build(dev(keys), dev(vals)) == B.BHT_OK
     check_table(t, params, keys, vals, n_queries=n)
     t.close()
+
+
+@pytest.mark.parametrize("b,n,lf", [(16, 1 << 20, 0.9), (16, 300007, 0.98), (8, 200003, 0.9),
+                                    (1, 100000, 0.8)])
+def test_eviction_count_equals_first_bucket_overflow(b, n, lf):
+    """A pair evicts on chip exactly when its first bucket already holds b
+    pairs, so the build's eviction count equals the first-bucket overflow
+    sum over buckets of max(0, X_j - b), X_j = pairs whose H_0 is bucket j,
+    computed here from the oracle's hash.  Every evicted pair then reads at
+    least one more bucket."""
+    B = bht()
+    scheme = "cht1" if b == 1 else "bcht"
+    keys, vals = workload(n, 31)
+    for s in range(6):
+        params = oracle.params_for(scheme, n, lf, 950 + s, b=b)
+        t, st = build_partitioned(params, keys, vals)
+        if st == B.BHT_OK:
+            break
+        t.close()
+    else:
+        pytest.fail("no partitioned build succeeded")
+    h0 = oracle.hash32_many(params.a[0], params.c[0], keys, params.m)
+    counts = np.bincount(h0.astype(np.int64), minlength=params.m)
+    expected = int(np.maximum(counts - b, 0).sum())
+    part, evicted, probes = B.bht_build_stats(t.handle)
+    assert part and evicted == expected
+    assert probes >= evicted
+    t.close()
+    # a concurrent build reports no partitioned statistics
+    t, st = build_partitioned(params, keys, vals, mode="concurrent")
+    assert st == B.BHT_OK
+    assert B.bht_build_stats(t.handle) == (False, 0, 0)
+    t.close()
