@@ -34,7 +34,8 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--runs", type=int, default=200, help="success workload: builds per load factor")
     ap.add_argument("--workload", default="bcht",
-                    choices=["bcht", "lfsweep", "schemes", "batched", "serve", "success"],
+                    choices=["bcht", "lfsweep", "schemes", "iceberg", "latency", "batched", "serve",
+                             "success"],
                     help="bcht: the headline BCHT workload; schemes: the comparison of "
                          "BCHT, BP2HT, two-level iceberg, 1CHT and 64-bit BCHT")
     ap.add_argument("--steps", type=int, default=5)
@@ -43,7 +44,7 @@ def parse():
     ap.add_argument("--lf", type=float, default=0.9)
     ap.add_argument("--bucket", type=int, default=16)
     ap.add_argument("--tile", type=int, default=None)
-    ap.add_argument("--schedule", default="default", choices=["default", "refill", "chunk"])
+    ap.add_argument("--schedule", default="default", choices=["default", "refill", "chunk", "parallel"])
     ap.add_argument("--grid", type=int, default=0, help="blocks per launch (0 = resident)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-log2n", type=int, default=24)
@@ -308,6 +309,22 @@ def run_schemes(args):
             if not wide:
                 p = entry["probes_per_key"]["insert" if k == "build" else k.replace("find_", "")]
                 entry["accesses_gps"][k] = round(p * n / (avg * 1e-3) / 1e9, 2)
+        if scheme == "iht":
+            # the early-exit find (a miss in a primary below t ends the query)
+            bht.bht_set_tuning(table.handle, iht_early_exit=True)
+            pr = torch.empty(n, dtype=torch.uint8, device=dev)
+            for qname in ("find_pos", "find_neg", "find_mix"):
+                times = []
+                for _ in range(args.steps):
+                    bht.bht_find(table.handle, d_q[qname], out_v, out_f, stream=stream)
+                    times.append(bht.bht_kernel_ms(table.handle)[1])
+                avg = float(np.mean(times))
+                entry[qname + "_early_ms"] = round(avg, 4)
+                entry[qname + "_early_gkeys_s"] = round(n / (avg * 1e-3) / 1e9, 4)
+                bht.bht_find_counted(table.handle, d_q[qname], out_v, out_f, pr, stream=stream)
+                entry["probes_per_key"][qname.replace("find_", "") + "_early"] = round(
+                    float(pr.sum(dtype=torch.int64).item()) / n, 4)
+            bht.bht_set_tuning(table.handle, iht_early_exit=False)
         results[name] = entry
         log("scheme %s: %s" % (name, json.dumps(entry)))
         table.close()
@@ -695,6 +712,165 @@ def run_lfsweep(args):
             f.write(line + "\n")
 
 
+ICEBERG_PERCENTS = (20, 30, 40, 50, 60, 70, 80)
+
+
+def run_iceberg(args):
+    """Iceberg threshold sweep (Section VII-A): one-level iceberg table, b = 16,
+    load factor 0.86, threshold t = floor(pct * 16 / 100) for pct in 20..80.
+    For each threshold: build rate, query rates at 100/0/50% positive with
+    the plain find (every candidate probed) and with the early-exit find
+    (stop after a miss in a primary below t), and probes per key from the
+    instrumented kernels, beside the paper's printed probe counts where it
+    gives them."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2108_07232_amd as bht
+
+    n = 1 << args.log2n
+    lf, b = 0.86, 16
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_probe_counts.json")))["iht"]
+    paper = {pct: (ins, pos) for pct, ins, pos in zip(golden["b16_lf086_thresholds_percent"],
+                                                      golden["b16_lf086_insert"]["value"],
+                                                      golden["b16_lf086_positive"]["value"])}
+    log("iceberg sweep: generating 2^%d inputs" % args.log2n)
+    keys, vals = datagen.unique_keys(n, args.seed), datagen.values(n, args.seed)
+    d_keys = torch.from_numpy(keys.view(np.int32)).to(dev)
+    d_vals = torch.from_numpy(vals.view(np.int32)).to(dev)
+    del keys, vals
+    d_q = {}
+    for qname, frac in (("find_pos", 1.0), ("find_neg", 0.0), ("find_mix", 0.5)):
+        d_q[qname] = torch.from_numpy(datagen.mixed_queries(n, n, frac, args.seed).view(np.int32)).to(dev)
+    out_v = torch.empty(n, dtype=torch.int32, device=dev)
+    out_f = torch.empty(n, dtype=torch.uint8, device=dev)
+    pr = torch.empty(n, dtype=torch.uint8, device=dev)
+    cap = datagen.capacity_for(n, lf)
+    results, seed = [], args.seed
+    for pct in ICEBERG_PERCENTS:
+        t_keys = (b * pct) // 100
+        table, failures = None, 0
+        for _ in range(5):
+            a, c = datagen.hash_constants(seed, 3)
+            t = bht.Table(cap, b, "iht", a, c, rng_seed=datagen.rng_seed(seed), iht_threshold=t_keys)
+            seed += 7919
+            if t.build(d_keys, d_vals) == bht.BHT_OK:
+                table = t
+                break
+            failures += 1
+            t.close()
+        if table is None:
+            results.append({"threshold_percent": pct, "threshold": t_keys, "built": False})
+            continue
+        bht.bht_enable_timing(table.handle, True)
+        ms = {k: [] for k in ("build", "find_pos", "find_neg", "find_mix",
+                              "find_pos_early", "find_neg_early", "find_mix_early")}
+        for step in range(args.warmup + args.steps):
+            if table.build(d_keys, d_vals) != bht.BHT_OK:
+                failures += 1
+                continue
+            rec = {"build": bht.bht_kernel_ms(table.handle)[0]}
+            for early in (False, True):
+                bht.bht_set_tuning(table.handle, iht_early_exit=early)
+                for qname in ("find_pos", "find_neg", "find_mix"):
+                    bht.bht_find(table.handle, d_q[qname], out_v, out_f, stream=stream)
+                    rec[qname + ("_early" if early else "")] = bht.bht_kernel_ms(table.handle)[1]
+            bht.bht_set_tuning(table.handle, iht_early_exit=False)
+            if step >= args.warmup:
+                for k, v in rec.items():
+                    ms[k].append(v)
+        total = torch.zeros(1, dtype=torch.int64, device=dev)
+        st = bht.bht_build_counted(table.handle, d_keys, d_vals, total)
+        probes = {"insert": int(total.item()) / n if st == bht.BHT_OK else None}
+        for early in (False, True):
+            bht.bht_set_tuning(table.handle, iht_early_exit=early)
+            for qname in ("find_pos", "find_neg", "find_mix"):
+                bht.bht_find_counted(table.handle, d_q[qname], out_v, out_f, pr, stream=stream)
+                key = qname.replace("find_", "") + ("_early" if early else "")
+                probes[key] = float(pr.sum(dtype=torch.int64).item()) / n
+        entry = {"threshold_percent": pct, "threshold": t_keys, "built": True,
+                 "build_failures": failures,
+                 "probes_per_key": {k: (round(v, 4) if v is not None else None)
+                                    for k, v in probes.items()}}
+        if pct in paper:
+            entry["paper_probes"] = {"insert": paper[pct][0], "pos": paper[pct][1], "neg": 3.0}
+        for k, v in ms.items():
+            if v:
+                avg = float(np.mean(v))
+                entry[k + "_ms"] = round(avg, 4)
+                entry[k + "_gkeys_s"] = round(n / (avg * 1e-3) / 1e9, 4)
+        results.append(entry)
+        log("iceberg %d%%: %s" % (pct, json.dumps(entry)))
+        table.close()
+        torch.cuda.empty_cache()
+    line = json.dumps({"workload": "iceberg", "n_keys": n, "load_factor": lf, "bucket_slots": b,
+                       "levels": 1, "results": results})
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "a") as f:
+            f.write(line + "\n")
+
+
+LATENCY_BATCHES = (1 << 8, 1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20)
+
+
+def run_latency(args):
+    """Query latency by batch size, serial probing (chunk schedule: bucket
+    H_i is read only after H_{i-1} missed and was full) against parallel
+    probing (all h buckets at once, Section II-A).  BCHT b = 16, h = 3, LF
+    0.9, 2^n keys; batches of 2^8 .. 2^20 queries, all positive or all
+    negative; median kernel time of 30 launches per point."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2108_07232_amd as bht
+
+    n = 1 << args.log2n
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    keys, vals = datagen.unique_keys(n, args.seed), datagen.values(n, args.seed)
+    a, c = datagen.hash_constants(args.seed, 3)
+    table = bht.Table(datagen.capacity_for(n, 0.9), 16, "bcht", a, c,
+                      rng_seed=datagen.rng_seed(args.seed))
+    st, _ = bht.bht_build_retry(table.handle, torch.from_numpy(keys.view(np.int32)).to(dev),
+                                torch.from_numpy(vals.view(np.int32)).to(dev), args.seed + 1)
+    if st != bht.BHT_OK:
+        raise RuntimeError("latency workload: build failed")
+    bht.bht_enable_timing(table.handle, True)
+    top = LATENCY_BATCHES[-1]
+    qs = {"pos": datagen.mixed_queries(n, top, 1.0, args.seed),
+          "neg": datagen.mixed_queries(n, top, 0.0, args.seed)}
+    d_q = {k: torch.from_numpy(v.view(np.int32)).to(dev) for k, v in qs.items()}
+    out_v = torch.empty(top, dtype=torch.int32, device=dev)
+    out_f = torch.empty(top, dtype=torch.uint8, device=dev)
+    results = {}
+    for sched in ("chunk", "parallel"):
+        bht.bht_set_tuning(table.handle, 0, sched)
+        for kind in ("pos", "neg"):
+            for nb in LATENCY_BATCHES:
+                times = []
+                for rep in range(33):
+                    bht.bht_find(table.handle, d_q[kind], out_v, out_f, n=nb, stream=stream)
+                    ms = bht.bht_kernel_ms(table.handle)[1]
+                    if rep >= 3:
+                        times.append(ms)
+                med = float(np.median(times))
+                results["%s_%s_%d" % (sched, kind, nb)] = {"us": round(med * 1e3, 2),
+                                                           "gq_s": round(nb / (med * 1e-3) / 1e9, 3)}
+        log("latency %s done" % sched)
+    table.close()
+    line = json.dumps({"workload": "latency", "n_keys": n, "load_factor": 0.9, "bucket_slots": 16,
+                       "hashes": 3, "batches": list(LATENCY_BATCHES), "results": results})
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "a") as f:
+            f.write(line + "\n")
+
+
 def run_success(args):
     """Build success rate (Section VII-D): the same keys built with `runs`
     different hash-constant sets per load factor; reports the fraction that
@@ -749,6 +925,20 @@ def main():
         if args.log2n == 28:
             args.log2n = 24
         run_success(args)
+        return
+    if args.workload == "latency":
+        import torch
+        torch.cuda.set_device(0)
+        if args.log2n == 28:
+            args.log2n = 24
+        run_latency(args)
+        return
+    if args.workload == "iceberg":
+        import torch
+        torch.cuda.set_device(0)
+        if args.log2n == 28:
+            args.log2n = 24
+        run_iceberg(args)
         return
     if args.workload == "lfsweep":
         import torch

@@ -194,7 +194,10 @@ bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint6
  * bucket_size; 0 keeps the default).  find_schedule: BHT_FIND_DEFAULT,
  * BHT_FIND_REFILL (a lane that finishes a query takes the next one) or
  * BHT_FIND_CHUNK (a wave answers 64 consecutive queries per chunk and writes
- * their results together).  grid_blocks: blocks of 256 threads per launch,
+ * their results together) or BHT_FIND_PARALLEL (BCHT and CHT1 only: all h
+ * candidate buckets of a query are read at once, Section II-A's parallel
+ * query: one memory latency per query instead of up to h, at h probes per
+ * query; results are identical).  grid_blocks: blocks of 256 threads per launch,
  * 0 = as many as the device keeps resident.  build_mode (BCHT and CHT1):
  * BHT_BUILD_CONCURRENT inserts every pair with the concurrent cuckoo
  * kernel (Section V-B); BHT_BUILD_PARTITIONED first groups the pairs by the
@@ -205,8 +208,19 @@ bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint6
  * insertion order, so layouts obey the same invariants.  It allocates a
  * library-owned workspace of about 8 bytes per pair on first use (kept
  * until bht_destroy).  BHT_BUILD_AUTO partitions builds of at least 2^20
- * pairs into tables whose memory the library owns (bht_create). */
-typedef enum { BHT_FIND_DEFAULT = 0, BHT_FIND_REFILL = 1, BHT_FIND_CHUNK = 2 } bht_find_schedule;
+ * pairs into tables whose memory the library owns (bht_create).
+ * iht_early_exit (iceberg tables only, else UNSUPPORTED): 1 makes a find
+ * stop after a miss in a primary bucket that holds fewer than
+ * iht_threshold keys, which proves absence because a key goes to a
+ * secondary bucket only once its primary holds that many (Section III-C);
+ * such a negative query costs one probe instead of three.  0 (default)
+ * probes every candidate, as Section V-D describes. */
+typedef enum {
+  BHT_FIND_DEFAULT = 0,
+  BHT_FIND_REFILL = 1,
+  BHT_FIND_CHUNK = 2,
+  BHT_FIND_PARALLEL = 3
+} bht_find_schedule;
 typedef enum {
   BHT_BUILD_AUTO = 0,
   BHT_BUILD_CONCURRENT = 1,
@@ -217,6 +231,7 @@ typedef struct {
   uint32_t find_schedule;
   uint32_t grid_blocks;
   uint32_t build_mode;
+  uint32_t iht_early_exit;
 } bht_tuning;
 bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning);
 bht_status bht_get_tuning(const bht_table* t, bht_tuning* tuning);

@@ -45,6 +45,7 @@ struct bht_table {
   hipEvent_t ev[4];        // build start/stop, find start/stop
   bool build_timed, find_timed;
   uint32_t build_mode;     // bht_build_mode
+  uint32_t iht_early_exit; // iceberg finds stop after a primary below the threshold
   void* d_part;            // partitioned build workspace (library-owned)
   uint64_t part_bytes;
   bool pending_partitioned;
@@ -254,10 +255,11 @@ constexpr uint32_t kDefaultSchedule = BHT_FIND_CHUNK;
 
 template <int B, int W, bool C>
 KernelSet cuckoo_set(uint32_t schedule) {
-  const bool chunk = schedule == BHT_FIND_CHUNK;
+  const bool chunk = schedule == BHT_FIND_CHUNK || schedule == BHT_FIND_PARALLEL;
   return {Kind::Cuckoo, (const void*)cuckoo_build_kernel<B, W, C>,
-          chunk ? (const void*)cuckoo_find_chunk_kernel<B, W, C>
-                : (const void*)cuckoo_find_kernel<B, W, C>,
+          schedule == BHT_FIND_PARALLEL ? (const void*)cuckoo_find_parallel_kernel<B, W, C>
+          : chunk                       ? (const void*)cuckoo_find_chunk_kernel<B, W, C>
+                                        : (const void*)cuckoo_find_kernel<B, W, C>,
           chunk};
 }
 
@@ -289,6 +291,8 @@ bool pick_t(bht_scheme scheme, uint32_t b, uint32_t b2, uint32_t w, uint32_t sch
     BHT_CASE(32, 8)
     BHT_CASE(32, 16)
 #undef BHT_CASE
+  } else if (schedule == BHT_FIND_PARALLEL) {
+    return false;                    // parallel probing: cuckoo tables only
   } else if (scheme == BHT_BP2HT) {
     if (b == 8 && w == 8) return *ks = p2_set<8, 8, C>(), true;
     if (b == 16 && w == 8) return *ks = p2_set<16, 8, C>(), true;
@@ -635,6 +639,7 @@ bht_status find32_enqueue(const bht_table* t, const uint32_t* q, uint64_t n, uin
     g.H = make_hash32(t->params, t->m, t->params.num_hashes);
     g.H2 = secondary_hash(t);
     g.rounds = t->params.num_hashes;
+    g.early_below = t->scheme == BHT_IHT && t->iht_early_exit ? t->params.iht_threshold : 0;
     reinterpret_cast<void (*)(SchemeFindArgs32)>(const_cast<void*>(ks.find))
         <<<grid, kBlock, 0, st>>>(g);
   }
@@ -954,8 +959,11 @@ bht_status bht_find64(const bht_table* t, const uint64_t* d_queries, uint64_t n,
 bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning) {
   if (!t || !tuning) return fail(BHT_ERR_INVALID_ARG, "null argument");
   const uint32_t w = tuning->tile_width ? tuning->tile_width : t->tile;
-  if (tuning->find_schedule > BHT_FIND_CHUNK) return fail(BHT_ERR_INVALID_ARG, "bad schedule");
+  if (tuning->find_schedule > BHT_FIND_PARALLEL) return fail(BHT_ERR_INVALID_ARG, "bad schedule");
   if (tuning->build_mode > BHT_BUILD_PARTITIONED) return fail(BHT_ERR_INVALID_ARG, "bad build mode");
+  if (tuning->iht_early_exit > 1) return fail(BHT_ERR_INVALID_ARG, "iht_early_exit must be 0 or 1");
+  if (tuning->iht_early_exit && t->scheme != BHT_IHT)
+    return fail(BHT_ERR_UNSUPPORTED, "early exit after the primary applies to iceberg tables");
   if (t->key_bits == 64) {
     if (w != 8) return fail(BHT_ERR_UNSUPPORTED, "64-bit tables read buckets with 8 lanes");
     t->grid_blocks = tuning->grid_blocks;
@@ -968,6 +976,7 @@ bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning) {
   t->find_schedule = tuning->find_schedule;
   t->grid_blocks = tuning->grid_blocks;
   t->build_mode = tuning->build_mode;
+  t->iht_early_exit = tuning->iht_early_exit;
   return BHT_OK;
 }
 
@@ -977,6 +986,7 @@ bht_status bht_get_tuning(const bht_table* t, bht_tuning* tuning) {
   tuning->find_schedule = t->find_schedule;
   tuning->grid_blocks = t->grid_blocks;
   tuning->build_mode = t->build_mode;
+  tuning->iht_early_exit = t->iht_early_exit;
   return BHT_OK;
 }
 

@@ -544,4 +544,53 @@ __global__ __launch_bounds__(kBlock) void cuckoo_find_chunk_kernel(FindArgs32 g)
   cuckoo_find_chunk_range<B, W, COUNT>(g, wave_range(g.n));
 }
 
+// Parallel probing (the alternative noted in Section II-A): all h candidate
+// buckets of a query are read at once, so a query costs one memory latency
+// instead of up to h dependent ones, at h probes per query.  A stored key
+// sits in exactly one bucket, so the first hit in hash order is the answer.
+// Chunk schedule as above.
+template <int B, int W, bool COUNT>
+__global__ __launch_bounds__(kBlock) void cuckoo_find_parallel_kernel(FindArgs32 g) {
+  const uint32_t lane = __lane_id();
+  const uint32_t tb = lane & ~(uint32_t)(W - 1);
+  const uint32_t lt = lane & (uint32_t)(W - 1);
+  const Range r = wave_range(g.n);
+  uint32_t q_next = (r.cursor + lane < r.end) ? g.queries[r.cursor + lane] : kEmptyKey;
+  for (uint64_t base = r.cursor; base < r.end; base += 64) {
+    const uint64_t idx = base + lane;
+    const bool valid = idx < r.end;
+    const uint32_t q = q_next;
+    q_next = (base + 64 + lane < r.end) ? g.queries[base + 64 + lane] : kEmptyKey;
+    const bool open = valid && q != kEmptyKey;
+    const uint64_t om = ballot(open);
+    Part<B / W> d[4][W];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i < (int)g.H.h) {
+        const uint32_t bucket = open ? hash32(g.H, i, q) : 0u;
+        tile_read<B, W>(g.slots, bucket, om, tb, lt, d[i]);
+      }
+    }
+    uint32_t out = kEmptyKey;
+    uint8_t found = 0;
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+      if (i < (int)g.H.h) {
+        bool hit = false, room = false;
+        uint32_t value = kEmptyKey;
+        tile_match<B, W>(d[i], q, tb, lt, &hit, &room, &value);
+        if (open && hit) {
+          out = value;
+          found = 1;
+        }
+      }
+    }
+    if (valid) {
+      g.out_v[idx] = out;
+      g.out_f[idx] = found;
+      if (COUNT) g.probes[idx] = open ? (uint8_t)g.H.h : (uint8_t)0;
+    }
+  }
+}
+
 }  // namespace bht

@@ -316,12 +316,15 @@ struct SchemeFindArgs32 {
   Hash32 H;
   Hash32 H2;
   uint32_t rounds;           // candidate buckets per query (2 or 3)
+  uint32_t early_below;      // iceberg: a miss in a primary holding fewer keys ends the query
 };
 
 // Queries of the stable schemes: probe the candidates in order and stop only
 // on a hit (Section V-C, Section V-D: no early exit).  Chunk schedule as the
 // cuckoo query.  With B2 > 0, rounds after the first read the secondary
-// array.
+// array.  early_below = t > 0 (iceberg): a key reaches a secondary bucket
+// only once its primary holds t keys (Section III-C), so a miss in a
+// primary holding fewer than t keys proves absence after one probe.
 template <int B, int B2, int W, bool COUNT>
 __global__ __launch_bounds__(kBlock) void stable_find_chunk_kernel(SchemeFindArgs32 g) {
   constexpr int BS2 = B2 ? B2 : B;
@@ -345,11 +348,13 @@ __global__ __launch_bounds__(kBlock) void stable_find_chunk_kernel(SchemeFindArg
       if (om == 0) break;
       bool hit = false;
       uint32_t value = kEmptyKey;
+      bool below = false;
       if (round == 0) {
         const uint32_t bucket = open ? hash32(g.H, 0, q) : 0u;
         Part<Slice<B, W>::S> d[W];
         tile_read_any<B, W>(g.slots, bucket, om, tb, lt, d);
         tile_match_any<B, W>(d, q, tb, lt, &hit, &value);
+        if (g.early_below) below = tile_load_any<B, W>(d, tb, lt) < g.early_below;
       } else {
         const uint32_t bucket = open ? hash32_dyn(HS, round, q) : 0u;
         Part<Slice<BS2, W>::S> d[W];
@@ -361,6 +366,8 @@ __global__ __launch_bounds__(kBlock) void stable_find_chunk_kernel(SchemeFindArg
         if (hit) {
           out = value;
           found = 1;
+          open = false;
+        } else if (below) {
           open = false;
         }
       }

@@ -55,7 +55,7 @@ def build_with_retries(scheme, n, lf, b, seed0, h=None, tile=None, tries=8):
 
 # -------------------------------------------- find on oracle-built layouts
 
-@pytest.mark.parametrize("schedule", ["refill", "chunk"])
+@pytest.mark.parametrize("schedule", ["refill", "chunk", "parallel"])
 @pytest.mark.parametrize("b,tile,n,lf", [
     (16, 8, 1 << 20, 0.9), (16, 4, 5000, 0.95), (16, 16, 4097, 0.9), (8, 8, 3001, 0.85),
     (8, 4, 777, 0.9), (32, 16, 6000, 0.95), (32, 8, 1000, 0.9), (4, 4, 2000, 0.8),
@@ -264,4 +264,30 @@ def test_build_retry_gives_up_after_max_attempts():
     t = B.Table(cap, 16, "bcht", a, c, max_chain=0)
     st, attempts = B.bht_build_retry(t.handle, dev(keys), dev(vals), 5, max_attempts=3)
     assert st == B.BHT_ERR_BUILD_FAILED and attempts == 3
+    t.close()
+
+
+@pytest.mark.parametrize("b,h", [(16, 3), (16, 2), (8, 4), (1, 3)])
+def test_parallel_probing_reads_every_candidate(b, h):
+    """Parallel probing reads all h buckets of every query (h probes, none
+    for the sentinel) and answers exactly as brute force."""
+    import torch
+    B = bht()
+    n = 40000
+    scheme = "cht1" if b == 1 else "bcht"
+    t, params, keys, vals = build_with_retries(scheme, n, 0.8, b, 9, h=h)
+    B.bht_set_tuning(t.handle, 0, "parallel")
+    q = datagen.mixed_queries(n, 2 * n, 0.5, 9)
+    q[5] = 0xFFFFFFFF
+    out_v = torch.empty(len(q), dtype=torch.int32, device="cuda")
+    out_f = torch.empty(len(q), dtype=torch.uint8, device="cuda")
+    pr = torch.empty(len(q), dtype=torch.uint8, device="cuda")
+    B.bht_find_counted(t.handle, dev(q), out_v, out_f, pr)
+    torch.cuda.synchronize()
+    bv, bf = oracle.brute_find32(keys, vals, q)
+    np.testing.assert_array_equal(host_u8(out_f), bf)
+    np.testing.assert_array_equal(host_u32(out_v), bv)
+    expect = np.full(len(q), h, dtype=np.uint8)
+    expect[5] = 0
+    np.testing.assert_array_equal(host_u8(pr), expect)
     t.close()

@@ -156,3 +156,35 @@ def test_power_of_two_places_in_less_loaded_bucket_when_uncontended():
     where = dict(zip(stored_keys.tolist(), (occ // 16).tolist()))
     assert all(where[int(k)] == int(b) for k, b in zip(keys, b0))
     t.close()
+
+
+@pytest.mark.parametrize("b,b2,thr,lf,n", [(16, 0, 13, 0.86, 1 << 18), (16, 0, 8, 0.8, 50001),
+                                           (16, 8, 16, 0.8, 1 << 18), (32, 0, 25, 0.9, 1 << 17)])
+def test_iceberg_early_exit_find(b, b2, thr, lf, n):
+    """Iceberg finds that stop after a miss in a primary below the threshold:
+    results equal brute force, and per-query probes equal the oracle's
+    early-exit find on the GPU's own layout (one probe for a negative query
+    whose primary holds fewer than t keys)."""
+    import torch
+    B = bht()
+    keys, vals = workload(n, 51)
+    for s in range(12):
+        p = iceberg_params(n, lf, 5100 + s, b=b, b2=b2, threshold=thr)
+        t = gpu_table(p)
+        st = t.build(dev(keys), dev(vals))
+        if st == B.BHT_OK:
+            break
+        t.close()
+    assert st == B.BHT_OK
+    B.bht_set_tuning(t.handle, iht_early_exit=True)
+    assert B.bht_get_tuning(t.handle)[4] == 1
+    p.early_exit = True
+    for frac in (1.0, 0.5, 0.0):
+        check_find(t, p, keys, vals, datagen.mixed_queries(n, n, frac, 52))
+    t.close()
+    # other schemes refuse the setting
+    pc = oracle.params_for("bcht", 1000, 0.5, 1)
+    t = B.Table(pc.m * 16, 16, "bcht", pc.a, pc.c)
+    with pytest.raises(B.BhtError):
+        B.bht_set_tuning(t.handle, iht_early_exit=True)
+    t.close()
