@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-SCHEMES = {"bcht": 0, "bp2ht": 1, "iht": 2, "cht1": 3}
+SCHEMES = {"bcht": 0, "bp2ht": 1, "iht": 2, "cht1": 3, "bcht_lb": 4}
 OK, FAILED, SENTINEL, BADARG = 0, 1, 2, 3
 EMPTY32 = 0xFFFFFFFF
 EMPTY64 = 0xFFFFFFFFFFFFFFFF
@@ -284,7 +284,7 @@ def params_for(scheme: str, n: int, load_factor: float, seed: int, b: int = 16, 
     """Geometry for n keys at a load factor: m = ceil(ceil(n / lf) / b)."""
     import datagen
     if h is None:
-        h = {"bcht": 3, "bp2ht": 2, "iht": 3, "cht1": 3}[scheme]
+        h = {"bcht": 3, "bp2ht": 2, "iht": 3, "cht1": 3, "bcht_lb": 3}[scheme]
     cap = datagen.capacity_for(n, load_factor)
     m = max(1, -(-cap // b))
     a, c = (datagen.hash_constants64 if wide else datagen.hash_constants)(seed, h)

@@ -123,6 +123,7 @@ static int check_params(const orc_params* p) {
   if (p->scheme == ORC_BP2HT && p->h != 2) return 0;
   if (p->scheme == ORC_IHT && p->h != 3) return 0;
   if (p->scheme == ORC_CHT1 && p->b != 1) return 0;
+  if (p->scheme < ORC_BCHT || p->scheme > ORC_BCHT_LB) return 0;
   if (p->scheme == ORC_IHT && p->b2 > 0 && p->m2 == 0) return 0;
   return 1;
 }
@@ -158,6 +159,53 @@ static int insert_cuckoo32(const orc_params* p, uint64_t* t, uint32_t k, uint32_
     while (j < p->h && !same_bucket(bucket32(p, j, key_of(cur)), B)) j++;
     if (j == p->h) j = p->h - 1;  /* not stored in a candidate: restart at H0 */
     B = bucket32(p, (j + 1) % p->h, key_of(cur));
+    chain++;
+  }
+}
+
+/* Load-balanced bucketed cuckoo insertion (Section III-A: the variation
+ * that inserts into the least loaded of the h buckets; Section IV,
+ * placement strategies).  Read all h candidate buckets and place at slot =
+ * load of the least loaded one with a free slot, ties going to the lowest
+ * hash index.  When every candidate is full, exchange the carried pair with
+ * a random resident of a random candidate bucket and continue with the
+ * evicted pair; the bucket it was just evicted from is not chosen again
+ * while another candidate differs from it.  The paper names no eviction
+ * rule for this variation; this one is the random walk of d-ary cuckoo
+ * hashing.  Reaching the eviction cap with every candidate full fails. */
+static int insert_lb32(const orc_params* p, uint64_t* t, uint32_t k, uint32_t v,
+                       uint32_t* rng, uint64_t* probes) {
+  uint64_t cur = pack(k, v);
+  uint64_t left = UINT64_MAX;           /* first slot of the bucket just left */
+  uint32_t chain = 0;
+  for (;;) {
+    bucket_ref cand[4];
+    uint32_t best = p->h, best_load = 0;
+    for (uint32_t i = 0; i < p->h; i++) {
+      cand[i] = bucket32(p, i, key_of(cur));
+      (*probes)++;
+      uint32_t l = load32(t, cand[i]);
+      if (l < cand[i].size && (best == p->h || l < best_load)) {
+        best = i;
+        best_load = l;
+      }
+    }
+    if (best < p->h) {
+      t[cand[best].first_slot + best_load] = cur;
+      return ORC_OK;
+    }
+    if (chain == p->max_chain) return ORC_FAILED;
+    uint32_t eligible[4], ne = 0;
+    for (uint32_t i = 0; i < p->h; i++)
+      if (cand[i].first_slot != left) eligible[ne++] = i;
+    *rng = orc_xorshift32(*rng);
+    uint32_t j = ne ? eligible[*rng % ne] : *rng % p->h;
+    *rng = orc_xorshift32(*rng);
+    uint32_t s = *rng % cand[j].size;
+    uint64_t victim = t[cand[j].first_slot + s];
+    t[cand[j].first_slot + s] = cur;
+    cur = victim;
+    left = cand[j].first_slot;
     chain++;
   }
 }
@@ -218,6 +266,7 @@ int orc_insert32(const orc_params* p, uint64_t* table, uint32_t key, uint32_t va
   if (key == EMPTY32) return ORC_SENTINEL;
   if (p->scheme == ORC_BP2HT) return insert_p2_32(p, table, key, val, probes);
   if (p->scheme == ORC_IHT) return insert_iceberg32(p, table, key, val, probes);
+  if (p->scheme == ORC_BCHT_LB) return insert_lb32(p, table, key, val, rng, probes);
   return insert_cuckoo32(p, table, key, val, rng, probes);
 }
 
@@ -308,8 +357,10 @@ static int find_in32(const uint64_t* t, bucket_ref B, uint32_t q, uint32_t* v) {
 /* Queries.  Cuckoo (Section V-B, Listing 4 as corrected): probe H0, H1, ...
  * in order; stop on a hit, and stop with a miss after a bucket that lacks
  * the key and is not full (insertion order never skips a bucket with room).
- * Power-of-two (Section V-C) and iceberg (Section III-C, V-D): probe every
- * candidate in order until a hit, no early exit on room.  Iceberg with
+ * Power-of-two (Section V-C), iceberg (Section III-C, V-D) and the
+ * load-balanced cuckoo table (Section III-A: placement may skip a bucket
+ * with room, so no early exit is valid): probe every candidate in order
+ * until a hit, no early exit on room.  Iceberg with
  * iht_early_exit: a key goes to a secondary bucket only when its primary
  * already holds at least t keys (Section III-C), and loads never decrease,
  * so a miss in a primary that holds fewer than t keys proves absence and

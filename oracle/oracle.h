@@ -22,7 +22,7 @@
 extern "C" {
 #endif
 
-enum { ORC_BCHT = 0, ORC_BP2HT = 1, ORC_IHT = 2, ORC_CHT1 = 3 };
+enum { ORC_BCHT = 0, ORC_BP2HT = 1, ORC_IHT = 2, ORC_CHT1 = 3, ORC_BCHT_LB = 4 };
 
 enum {
   ORC_OK = 0,
@@ -32,7 +32,7 @@ enum {
 };
 
 typedef struct {
-  int32_t scheme;       /* ORC_BCHT, ORC_BP2HT, ORC_IHT or ORC_CHT1             */
+  int32_t scheme;       /* ORC_BCHT, ORC_BP2HT, ORC_IHT, ORC_CHT1, ORC_BCHT_LB   */
   uint32_t b;           /* slots per (primary) bucket                            */
   uint64_t m;           /* number of (primary) buckets                           */
   uint32_t h;           /* number of hash functions (IHT: 3 = primary, s0, s1)  */

@@ -441,8 +441,8 @@ def _probe_stats(scheme, n, lf, b, h=None, threshold=0, seeds=range(1, 8)):
         neg = datagen.negative_keys(n, n, seed)
         _, _, pp, per_pos = oracle.find32(params, table, pos)
         _, _, pn, _ = oracle.find32(params, table, neg)
-        return dict(params=params, table=table, keys=keys, insert=ins / n, pos=pp / n,
-                    neg=pn / n, per_pos=per_pos, pos_q=pos)
+        return dict(params=params, table=table, keys=keys, vals=vals, insert=ins / n,
+                    pos=pp / n, neg=pn / n, per_pos=per_pos, pos_q=pos)
     pytest.fail("no successful build")
 
 
@@ -550,3 +550,55 @@ def test_iceberg_early_exit_find_equals_brute_force(b2, t, lf, both):
     assert (neg & ~below).any()
     if both:        # a low threshold leaves (almost) no primary below it
         assert (neg & below).any()
+
+
+# ------------------------------------------- load-balanced cuckoo table
+
+@pytest.mark.parametrize("b,h,lf", [(16, 3, 0.9), (16, 3, 0.97), (16, 2, 0.9), (8, 3, 0.9),
+                                    (32, 2, 0.95), (16, 4, 0.98)])
+def test_load_balanced_cuckoo_find_equals_brute_force(b, h, lf):
+    """Layouts satisfy the invariants that hold without early exit, lookups
+    equal the plain definition, a negative query reads all h buckets, and
+    insertion reads h buckets per placement attempt."""
+    n = 20000
+    s = _probe_stats("bcht_lb", n, lf, b, h=h)
+    params, table, keys, vals = s["params"], s["table"], s["keys"], s["vals"]
+    assert oracle.check32(params, table, keys, vals) == (0, "ok")
+    q = datagen.mixed_queries(n, 2 * n, 0.5, 3)
+    v, f, _, per = oracle.find32(params, table, q)
+    bv, bf = oracle.brute_find32(keys, vals, q)
+    np.testing.assert_array_equal(f, bf)
+    np.testing.assert_array_equal(v, bv)
+    assert np.all(per[f == 0] == h)
+    assert s["neg"] == h
+    ins = int(round(s["insert"] * n))
+    assert ins >= h * n and ins % h == 0
+
+
+def test_load_balanced_two_hashes_equals_power_of_two_without_evictions():
+    """With two hashes and no bucket pair ever full, the load-balanced rule
+    (least loaded, ties to H0) is the power-of-two rule: both serial builds
+    give the same layout, word for word, though written separately."""
+    n = 30000
+    keys, vals = datagen.unique_keys(n, 5), datagen.values(n, 5)
+    lb = oracle.params_for("bcht_lb", n, 0.7, 5, b=16, h=2)
+    p2 = oracle.params_for("bp2ht", n, 0.7, 5, b=16)
+    assert lb.a == p2.a and lb.c == p2.c and lb.m == p2.m
+    st1, t1, ins1 = oracle.build32(lb, keys, vals)
+    st2, t2, ins2 = oracle.build32(p2, keys, vals)
+    assert st1 == st2 == oracle.OK and ins1 == ins2 == 2 * n
+    np.testing.assert_array_equal(t1, t2)
+
+
+def test_load_balanced_eviction_fires_and_stays_valid():
+    """Past the two-choice limit the load-balanced table must evict (insert
+    probes above h per key) and its layout stays valid; plain power-of-two
+    fails at the same load."""
+    n = 1 << 16
+    keys, vals = datagen.unique_keys(n, 6), datagen.values(n, 6)
+    p2 = oracle.params_for("bp2ht", n, 0.95, 6, b=8)
+    assert oracle.build32(p2, keys, vals)[0] == oracle.FAILED
+    lb = oracle.params_for("bcht_lb", n, 0.95, 6, b=8, h=2)
+    st, table, ins = oracle.build32(lb, keys, vals)
+    assert st == oracle.OK and ins > 2 * n
+    assert oracle.check32(lb, table, keys, vals) == (0, "ok")
