@@ -194,6 +194,8 @@ SCHEME_CONFIGS = [
     ("iht_two_level", "iht", 16, 3, 0.9, 8, False),
     ("cht1", "cht1", 1, 3, 0.8, 0, False),
     ("bcht64", "bcht", 8, 3, 0.9, 0, True),
+    ("bcht_lb", "bcht_lb", 16, 3, 0.9, 0, False),
+    ("bcht_lb_h2", "bcht_lb", 16, 2, 0.9, 0, False),
 ]
 
 
@@ -594,6 +596,8 @@ SUCCESS_SWEEP = [
     ("bp2ht_b32", "bp2ht", 32, 2, 0, (0.88, 0.89, 0.90, 0.91, 0.92)),
     ("iht_b32_t80", "iht", 32, 3, 25, (0.88, 0.89, 0.90, 0.91, 0.92)),
     ("cht1_h4", "cht1", 1, 4, 0, (0.85, 0.86, 0.87, 0.88, 0.89)),
+    ("bcht_lb_b16", "bcht_lb", 16, 3, 0, (0.97, 0.98, 0.99, 0.995, 1.0)),
+    ("bcht_lb_b16_h2", "bcht_lb", 16, 2, 0, (0.95, 0.96, 0.97, 0.98, 0.99)),
 ]
 
 

@@ -19,6 +19,12 @@
  *              III-C, V-D); optionally with a separate secondary level.
  *   BHT_CHT1   cuckoo table with one slot per bucket (bucket_size = 1), the
  *              classic GPU cuckoo layout the paper compares against.
+ *   BHT_BCHT_LB load-balanced bucketed cuckoo table (Section III-A's
+ *              variation): a pair goes to the least loaded of its h buckets
+ *              (ties to the lowest hash); when all are full it evicts a random
+ *              resident of a random candidate other than the bucket it was
+ *              just evicted from; queries probe every candidate (no early
+ *              exit is valid).  32-bit keys, h = 2..4, bucket size 8/16/32.
  *
  * Device memory layout (library-owned, 256-byte aligned):
  *   32-bit tables: one 8-byte slot per pair, key in the low 32 bits and value
@@ -59,7 +65,8 @@ typedef enum {
   BHT_BCHT = 0,
   BHT_BP2HT = 1,
   BHT_IHT = 2,
-  BHT_CHT1 = 3
+  BHT_CHT1 = 3,
+  BHT_BCHT_LB = 4
 } bht_scheme;
 
 typedef enum {

@@ -13,8 +13,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbht.so")
 
-BHT_BCHT, BHT_BP2HT, BHT_IHT, BHT_CHT1 = 0, 1, 2, 3
-SCHEMES = {"bcht": BHT_BCHT, "bp2ht": BHT_BP2HT, "iht": BHT_IHT, "cht1": BHT_CHT1}
+BHT_BCHT, BHT_BP2HT, BHT_IHT, BHT_CHT1, BHT_BCHT_LB = 0, 1, 2, 3, 4
+SCHEMES = {"bcht": BHT_BCHT, "bp2ht": BHT_BP2HT, "iht": BHT_IHT, "cht1": BHT_CHT1,
+           "bcht_lb": BHT_BCHT_LB}
 
 STATUS = {
     0: "BHT_OK", 1: "BHT_ERR_INVALID_ARG", 2: "BHT_ERR_CAPACITY", 3: "BHT_ERR_SENTINEL_KEY",

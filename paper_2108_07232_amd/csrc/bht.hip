@@ -212,6 +212,10 @@ bool valid_params(const bht_params& p, bht_scheme scheme, uint32_t b, std::strin
       if (p.key_bits != 32 || p.num_hashes != 2 || (b != 8 && b != 16 && b != 32))
         return *why = "BP2HT needs 32-bit keys, 2 hashes and bucket size 8, 16 or 32", false;
       break;
+    case BHT_BCHT_LB:
+      if (p.key_bits != 32 || p.num_hashes < 2 || (b != 8 && b != 16 && b != 32))
+        return *why = "BCHT_LB needs 32-bit keys, 2..4 hashes and bucket size 8, 16 or 32", false;
+      break;
     case BHT_IHT:
       if (p.key_bits != 32 || p.num_hashes != 3 || (b != 16 && b != 32))
         return *why = "IHT needs 32-bit keys, 3 hashes and bucket size 16 or 32", false;
@@ -240,7 +244,7 @@ uint32_t default_tile(bht_scheme scheme, uint32_t b) {
 
 // --------------------------------------------------------------- dispatch
 
-enum class Kind { Cuckoo, P2, Iceberg };
+enum class Kind { Cuckoo, P2, Iceberg, LoadBalanced };
 
 // The kernels of one table configuration (bucket size, secondary bucket
 // size, tile width, probe counting, query schedule).
@@ -269,6 +273,12 @@ KernelSet p2_set() {
           (const void*)stable_find_chunk_kernel<B, 0, W, C>, true};
 }
 
+template <int B, int W, bool C>
+KernelSet lb_set() {
+  return {Kind::LoadBalanced, (const void*)lb_build_kernel<B, W, C>,
+          (const void*)stable_find_chunk_kernel<B, 0, W, C>, true};
+}
+
 template <int B, int B2, int W, bool C>
 KernelSet iceberg_set() {
   return {Kind::Iceberg, (const void*)iceberg_build_kernel<B, B2, W, C>,
@@ -293,6 +303,10 @@ bool pick_t(bht_scheme scheme, uint32_t b, uint32_t b2, uint32_t w, uint32_t sch
 #undef BHT_CASE
   } else if (schedule == BHT_FIND_PARALLEL) {
     return false;                    // parallel probing: cuckoo tables only
+  } else if (scheme == BHT_BCHT_LB) {
+    if (b == 8 && w == 8) return *ks = lb_set<8, 8, C>(), true;
+    if (b == 16 && w == 8) return *ks = lb_set<16, 8, C>(), true;
+    if (b == 32 && w == 16) return *ks = lb_set<32, 16, C>(), true;
   } else if (scheme == BHT_BP2HT) {
     if (b == 8 && w == 8) return *ks = p2_set<8, 8, C>(), true;
     if (b == 16 && w == 8) return *ks = p2_set<16, 8, C>(), true;
@@ -566,7 +580,7 @@ bht_status build32_enqueue(bht_table* t, const uint32_t* keys, const uint32_t* v
     const uint64_t grid_items = ks.kind == Kind::Cuckoo ? n : (n + 31) / 32;
     const int grid = grid_for(ks.build, grid_items, t->grid_blocks);
     if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
-    if (ks.kind == Kind::Cuckoo) {
+    if (ks.kind == Kind::Cuckoo || ks.kind == Kind::LoadBalanced) {
       BuildArgs32 g;
       g.slots = t->d_slots;
       g.keys = keys;
@@ -840,7 +854,7 @@ bht_status bht_params_from_seed(uint64_t seed, bht_scheme scheme, uint32_t key_b
   bht_params p{};
   switch (scheme) {
     case BHT_BP2HT: p.num_hashes = 2; break;
-    case BHT_BCHT: case BHT_IHT: case BHT_CHT1: p.num_hashes = 3; break;
+    case BHT_BCHT: case BHT_IHT: case BHT_CHT1: case BHT_BCHT_LB: p.num_hashes = 3; break;
     default: return fail(BHT_ERR_INVALID_ARG, "unknown scheme");
   }
   p.key_bits = key_bits;

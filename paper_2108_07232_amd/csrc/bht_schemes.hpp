@@ -1,7 +1,8 @@
-// Stable comparison schemes on the same tile skeleton as the cuckoo table:
-// bucketed power-of-two choices (Section III-B, Section V-C) and iceberg
-// hashing (Section III-C, Section V-D), plus one query kernel for every
-// scheme whose probe sequence is fixed (no eviction).
+// Comparison schemes on the same tile skeleton as the cuckoo table:
+// bucketed power-of-two choices (Section III-B, Section V-C), iceberg
+// hashing (Section III-C, Section V-D) and the load-balanced cuckoo table
+// (Section III-A's variation), plus one query kernel for every scheme whose
+// queries cannot stop early on a bucket with room.
 //
 // Insertion follows the cuckoo kernel's rules for concurrency: a bucket is
 // read once, the lane then claims slot = load with a CAS and walks to the
@@ -174,6 +175,150 @@ __global__ __launch_bounds__(kBlock) void p2_build_kernel(SchemeArgs32 g) {
       } else {
         flags |= kFlagFailed;
         active = false;
+      }
+    }
+  }
+  if (flags) atomicOr(g.status, flags);
+  if (COUNT) {
+    const uint32_t total = wave_sum(probes);
+    if (__lane_id() == 0 && total) atomicAdd(g.probe_total, (unsigned long long)total);
+  }
+}
+
+enum : uint32_t { kLbRead = 0, kLbPick = 1, kLbWalk = 2, kLbEvict = 3 };
+
+// Load-balanced cuckoo insertion (Section III-A's variation that inserts
+// into the least loaded of the h buckets): read all h candidates, claim a
+// slot in the least loaded one with room per that read (ties to the lowest
+// hash index), walking on CAS failures; a walk that reaches the end proves
+// its bucket full and the lane turns to the next candidate from the same
+// read.  With every candidate full the pair is exchanged with a random
+// resident of a random candidate other than the bucket it was just evicted
+// from, and the evicted pair starts over with its own candidates.  A bucket
+// is taken as full only when a read showed b pairs (reads can only
+// under-report) or a walk failed on every slot, so exchanges hit occupied
+// slots and occupied slots stay a prefix; no bucket is read twice for the
+// same pair, so no lane can spin on a stale copy.
+template <int B, int W, bool COUNT>
+__global__ __launch_bounds__(kBlock) void lb_build_kernel(BuildArgs32 g) {
+  const uint32_t lane = __lane_id();
+  const uint32_t tb = lane & ~(uint32_t)(W - 1);
+  const uint32_t lt = lane & (uint32_t)(W - 1);
+  const uint32_t h = g.H.h;
+  const Range r = wave_range(g.n);
+  uint32_t rng = g.rng_seed ^ lane_salt();
+  if (rng == 0) rng = 0x2545F491u;
+  Feed<uint32_t> fk, fv;
+  fk.init(g.keys, r, kEmptyKey);
+  fv.init(g.vals, r, 0u);
+  bool active = false;
+  uint32_t key = 0, val = 0, chain = 0, left = ~0u, phase = kLbRead;
+  uint32_t cb[4] = {0u, 0u, 0u, 0u};                       // candidate buckets
+  uint32_t cl[4] = {(uint32_t)B, (uint32_t)B, (uint32_t)B, (uint32_t)B};  // their loads
+  uint32_t cur = 0, slot = 0, probes = 0, flags = 0;
+
+  for (;;) {
+    uint64_t idx;
+    const int64_t off = fk.claim(!active, &idx);
+    fv.claim(!active, &idx);
+    const uint32_t k_new = fk.value_at(off);
+    const uint32_t v_new = fv.value_at(off);
+    fk.advance(kEmptyKey);
+    fv.advance(0u);
+    if (off >= 0) {
+      if (k_new == kEmptyKey) {
+        flags |= kFlagSentinel;
+      } else {
+        active = true;
+        key = k_new;
+        val = v_new;
+        chain = 0;
+        left = ~0u;
+        phase = kLbRead;
+      }
+    }
+    if (ballot(active) == 0) {
+      if (fk.cursor >= fk.end) break;
+      continue;
+    }
+    const uint64_t rd = ballot(active && phase == kLbRead);
+    if (rd) {
+      const bool me = active && phase == kLbRead;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i < (int)h) {
+          const uint32_t bi = me ? hash32(g.H, i, key) : 0u;
+          Part<B / W> d[W];
+          tile_read<B, W>(g.slots, bi, rd, tb, lt, d);
+          const uint32_t li = tile_load<B, W>(d, tb, lt);
+          if (me) {
+            cb[i] = bi;
+            cl[i] = li;
+          }
+        }
+      }
+      if (me) {
+        if (COUNT) probes += h;
+        phase = kLbPick;
+      }
+    }
+    if (active && phase == kLbPick) {
+      uint32_t best = 4, bl = (uint32_t)B;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i < (int)h && cl[i] < bl) {
+          best = i;
+          bl = cl[i];
+        }
+      if (best < 4) {
+        cur = best;
+        slot = bl;
+        phase = kLbWalk;
+      } else {
+        phase = kLbEvict;
+      }
+    }
+    const uint64_t pair = ((uint64_t)val << 32) | key;
+    if (active && phase == kLbWalk) {
+      const uint64_t old = cas64(g.slots + (uint64_t)sel4(cb, cur) * B + slot, kEmptyPair, pair);
+      if (old == kEmptyPair) {
+        active = false;
+      } else if (++slot == (uint32_t)B) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if ((uint32_t)i == cur) cl[i] = (uint32_t)B;   // proven full
+        phase = kLbPick;
+      }
+    } else if (active && phase == kLbEvict) {
+      if (chain >= g.max_chain) {
+        flags |= kFlagFailed;
+        active = false;
+      } else {
+        uint32_t ne = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i < (int)h && cb[i] != left) ++ne;
+        rng = xorshift32(rng);
+        const uint32_t want = rng % (ne ? ne : h);
+        uint32_t target = cb[0], seen = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (i < (int)h && (ne == 0 || cb[i] != left)) {
+            if (seen == want) target = cb[i];
+            ++seen;
+          }
+        }
+        rng = xorshift32(rng);
+        const uint64_t old = xchg64(g.slots + (uint64_t)target * B + (rng % (uint32_t)B), pair);
+        if (old == kEmptyPair) {
+          active = false;
+        } else {
+          key = (uint32_t)old;
+          val = (uint32_t)(old >> 32);
+          left = target;
+          ++chain;
+          phase = kLbRead;
+        }
       }
     }
   }

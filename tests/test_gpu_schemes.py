@@ -188,3 +188,58 @@ def test_iceberg_early_exit_find(b, b2, thr, lf, n):
     with pytest.raises(B.BhtError):
         B.bht_set_tuning(t.handle, iht_early_exit=True)
     t.close()
+
+
+@pytest.mark.parametrize("b,h,lf,n", [(16, 3, 0.9, 1 << 18), (16, 3, 0.97, 1 << 17),
+                                      (16, 2, 0.9, 100003), (8, 3, 0.9, 1 << 17),
+                                      (32, 2, 0.95, 1 << 17), (16, 4, 0.98, 50000)])
+def test_load_balanced_cuckoo_build_find_parity(b, h, lf, n):
+    """Load-balanced cuckoo table on the GPU: the layout satisfies the
+    oracle's invariants (no early-exit property is claimed), lookups equal
+    brute force, per-query probes equal the oracle's on the GPU layout, and
+    insertion reads h buckets per placement attempt."""
+    import torch
+    B = bht()
+    keys, vals = workload(n, 61)
+    for s in range(10):
+        p = oracle.params_for("bcht_lb", n, lf, 6100 + s, b=b, h=h)
+        t = gpu_table(p)
+        total = torch.zeros(1, dtype=torch.int64, device="cuda")
+        st = B.bht_build_counted(t.handle, dev(keys), dev(vals), total)
+        if st == B.BHT_OK:
+            break
+        assert st == B.BHT_ERR_BUILD_FAILED
+        t.close()
+    assert st == B.BHT_OK
+    code, msg = oracle.check32(p, t.download(), keys, vals)
+    assert code == 0, msg
+    ins = int(total.item())
+    assert ins >= h * n and ins % h == 0
+    for frac in (1.0, 0.5, 0.0):
+        check_find(t, p, keys, vals, datagen.mixed_queries(n, n, frac, 62))
+    # an uninstrumented rebuild is valid too
+    assert t.build(dev(keys), dev(vals)) == B.BHT_OK
+    assert oracle.check32(p, t.download(), keys, vals)[0] == 0
+    t.close()
+
+
+def test_load_balanced_cuckoo_reaches_loads_power_of_two_cannot():
+    """With two hashes and 8-slot buckets, power-of-two choices fails at load
+    0.95 while the load-balanced table, which can evict, builds."""
+    B = bht()
+    n = 1 << 16
+    keys, vals = workload(n, 63)
+    p = oracle.params_for("bp2ht", n, 0.95, 63, b=8)
+    t = gpu_table(p)
+    assert t.build(dev(keys), dev(vals)) == B.BHT_ERR_BUILD_FAILED
+    t.close()
+    for s in range(6):
+        p = oracle.params_for("bcht_lb", n, 0.95, 6300 + s, b=8, h=2)
+        t = gpu_table(p)
+        st = t.build(dev(keys), dev(vals))
+        if st == B.BHT_OK:
+            break
+        t.close()
+    assert st == B.BHT_OK
+    assert oracle.check32(p, t.download(), keys, vals)[0] == 0
+    t.close()
