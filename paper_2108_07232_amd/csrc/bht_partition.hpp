@@ -36,11 +36,17 @@
 
 namespace bht {
 
+// Threads per counting / scatter block and pairs staged per sub-tile
+// (compile-time tuning; the sub-tile is 8 pairs per thread).
+#ifndef BHT_PASS_BLOCK
+#define BHT_PASS_BLOCK 512
+#endif
 constexpr int kPartBlock = 256;                        // threads per scan block
-constexpr int kPassBlock = 512;                        // threads per counting / scatter block
-constexpr int kPartSub = 4096;                         // pairs staged per sub-tile
+constexpr int kPassBlock = BHT_PASS_BLOCK;
+constexpr int kPartSub = 8 * kPassBlock;
 constexpr int kPartPer = kPartSub / kPassBlock;        // pairs per thread per sub-tile
-constexpr uint32_t kPartChunk = 16 * kPartSub;         // pairs per partition block
+constexpr uint32_t kPartChunk = 65536;                 // pairs per partition block
+static_assert(kPartChunk % kPartSub == 0, "a chunk is a whole number of sub-tiles");
 constexpr uint32_t kMaxFan = 1024;                     // digits of the first pass, at most
 constexpr uint32_t kFan2 = 256;                        // digits of the second pass
 constexpr int kBinBlock = 512;                         // threads per bin placement block
