@@ -129,7 +129,7 @@ def kernel_source_sha():
     """SHA-256 prefix of the sources that define the build and find kernels."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("bht_hash.hpp", "bht_kernels.hpp"):
+    for name in ("bht_hash.hpp", "bht_kernels.hpp", "bht_partition.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2108_07232_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
