@@ -493,55 +493,89 @@ __global__ __launch_bounds__(kBlock) void cuckoo_find_kernel(FindArgs32 g) {
   }
 }
 
-// Same query, chunk schedule: a wave answers 64 consecutive queries per
-// chunk in up to h rounds (round i probes H_i for the queries still open),
-// then writes the 64 results with one coalesced store each; the next
-// chunk's queries are loaded while the current chunk is probed.
-template <int B, int W, bool COUNT>
+// Same query, chunk schedule: a wave answers Q*64 consecutive queries per
+// chunk (Q per lane) in up to h rounds (round i probes H_i for the queries
+// still open), then writes the results with coalesced stores; the next
+// chunk's queries are loaded while the current chunk is probed.  Q > 1 puts
+// more bucket reads in flight per wave in the first round.
+template <int B, int W, bool COUNT, int Q = 1>
 __device__ __forceinline__ void cuckoo_find_chunk_range(const FindArgs32& g, Range r) {
   const uint32_t lane = __lane_id();
   const uint32_t tb = lane & ~(uint32_t)(W - 1);
   const uint32_t lt = lane & (uint32_t)(W - 1);
-  uint32_t q_next = (r.cursor + lane < r.end) ? g.queries[r.cursor + lane] : kEmptyKey;
-  for (uint64_t base = r.cursor; base < r.end; base += 64) {
-    const uint64_t idx = base + lane;
-    const bool valid = idx < r.end;
-    const uint32_t q = q_next;
-    q_next = (base + 64 + lane < r.end) ? g.queries[base + 64 + lane] : kEmptyKey;
-    bool open = valid && q != kEmptyKey;
-    uint32_t out = kEmptyKey, rounds = 0;
-    uint8_t found = 0;
+  constexpr uint32_t C = 64 * Q;
+  uint32_t q_next[Q];
+#pragma unroll
+  for (int u = 0; u < Q; ++u)
+    q_next[u] = (r.cursor + u * 64 + lane < r.end) ? g.queries[r.cursor + u * 64 + lane] : kEmptyKey;
+  for (uint64_t base = r.cursor; base < r.end; base += C) {
+    uint32_t q[Q], out[Q], rounds[Q];
+    bool open[Q], valid[Q];
+    uint8_t found[Q];
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+      const uint64_t idx = base + u * 64 + lane;
+      valid[u] = idx < r.end;
+      q[u] = q_next[u];
+      q_next[u] = (base + C + u * 64 + lane < r.end) ? g.queries[base + C + u * 64 + lane]
+                                                     : kEmptyKey;
+      open[u] = valid[u] && q[u] != kEmptyKey;
+      out[u] = kEmptyKey;
+      rounds[u] = 0;
+      found[u] = 0;
+    }
     for (uint32_t round = 0; round < g.H.h; ++round) {
-      const uint64_t om = ballot(open);
-      if (om == 0) break;
-      const uint32_t bucket = open ? hash32_dyn(g.H, round, q) : 0u;
-      Part<B / W> d[W];
-      tile_read<B, W>(g.slots, bucket, om, tb, lt, d);
-      bool hit = false, room = false;
-      uint32_t value = kEmptyKey;
-      tile_match<B, W>(d, q, tb, lt, &hit, &room, &value);
-      if (open) {
-        rounds = round + 1;
-        if (hit) {
-          out = value;
-          found = 1;
-          open = false;
-        } else if (room) {
-          open = false;
+      uint64_t om[Q], any = 0;
+#pragma unroll
+      for (int u = 0; u < Q; ++u) {
+        om[u] = ballot(open[u]);
+        any |= om[u];
+      }
+      if (any == 0) break;
+      Part<B / W> d[Q][W];
+#pragma unroll
+      for (int u = 0; u < Q; ++u) {
+        const uint32_t bucket = open[u] ? hash32_dyn(g.H, round, q[u]) : 0u;
+        tile_read<B, W>(g.slots, bucket, om[u], tb, lt, d[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < Q; ++u) {
+        bool hit = false, room = false;
+        uint32_t value = kEmptyKey;
+        tile_match<B, W>(d[u], q[u], tb, lt, &hit, &room, &value);
+        if (open[u]) {
+          rounds[u] = round + 1;
+          if (hit) {
+            out[u] = value;
+            found[u] = 1;
+            open[u] = false;
+          } else if (room) {
+            open[u] = false;
+          }
         }
       }
     }
-    if (valid) {
-      g.out_v[idx] = out;
-      g.out_f[idx] = found;
-      if (COUNT) g.probes[idx] = (uint8_t)rounds;
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+      if (valid[u]) {
+        const uint64_t idx = base + u * 64 + lane;
+        g.out_v[idx] = out[u];
+        g.out_f[idx] = found[u];
+        if (COUNT) g.probes[idx] = (uint8_t)rounds[u];
+      }
     }
   }
 }
 
+// Queries per lane per chunk of the single-table query kernel (compile-time
+// tuning).
+#ifndef BHT_FIND_QPL
+#define BHT_FIND_QPL 1
+#endif
+
 template <int B, int W, bool COUNT>
 __global__ __launch_bounds__(kBlock) void cuckoo_find_chunk_kernel(FindArgs32 g) {
-  cuckoo_find_chunk_range<B, W, COUNT>(g, wave_range(g.n));
+  cuckoo_find_chunk_range<B, W, COUNT, BHT_FIND_QPL>(g, wave_range(g.n));
 }
 
 // Parallel probing (the alternative noted in Section II-A): all h candidate
