@@ -684,6 +684,8 @@ def run_lfsweep(args):
         total = torch.zeros(1, dtype=torch.int64, device=dev)
         st = bht.bht_build_counted(table.handle, d_keys, d_vals, total)
         probes = {"insert": int(total.item()) / n if st == bht.BHT_OK else None}
+        while st != bht.BHT_OK:       # a concurrent build near the limit can fail: rebuild
+            st = table.build(d_keys, d_vals)
         pr = torch.empty(n, dtype=torch.uint8, device=dev)
         for qname in ("find_pos", "find_neg", "find_mix"):
             bht.bht_find_counted(table.handle, d_q[qname], out_v, out_f, pr, stream=stream)
@@ -789,6 +791,14 @@ def run_iceberg(args):
         total = torch.zeros(1, dtype=torch.int64, device=dev)
         st = bht.bht_build_counted(table.handle, d_keys, d_vals, total)
         probes = {"insert": int(total.item()) / n if st == bht.BHT_OK else None}
+        tries = 0
+        while st != bht.BHT_OK and tries < 20:   # near the limit a build can fail: rebuild
+            st = table.build(d_keys, d_vals)
+            tries += 1
+        if st != bht.BHT_OK:
+            results.append({"threshold_percent": pct, "threshold": t_keys, "built": False})
+            table.close()
+            continue
         for early in (False, True):
             bht.bht_set_tuning(table.handle, iht_early_exit=early)
             for qname in ("find_pos", "find_neg", "find_mix"):

@@ -439,7 +439,7 @@ PartLayout part_layout(const PartPlan& P, uint64_t n) {
 }
 
 bool use_partitioned(const bht_table* t, uint64_t n, bool counting) {
-  if (counting || n == 0) return false;
+  if (counting || n == 0 || n >= (1ull << 32)) return false;
   if (t->scheme != BHT_BCHT && t->scheme != BHT_CHT1) return false;
   if (t->build_mode == BHT_BUILD_CONCURRENT) return false;
   PartPlan P;

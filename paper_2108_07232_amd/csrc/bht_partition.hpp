@@ -39,11 +39,14 @@ namespace bht {
 // Threads per counting / scatter block and pairs staged per sub-tile
 // (compile-time tuning; the sub-tile is 8 pairs per thread).
 #ifndef BHT_PASS_BLOCK
-#define BHT_PASS_BLOCK 512
+#define BHT_PASS_BLOCK 1024
+#endif
+#ifndef BHT_PASS_PER
+#define BHT_PASS_PER 8
 #endif
 constexpr int kPartBlock = 256;                        // threads per scan block
 constexpr int kPassBlock = BHT_PASS_BLOCK;
-constexpr int kPartSub = 8 * kPassBlock;
+constexpr int kPartSub = BHT_PASS_PER * kPassBlock;
 constexpr int kPartPer = kPartSub / kPassBlock;        // pairs per thread per sub-tile
 constexpr uint32_t kPartChunk = 65536;                 // pairs per partition block
 static_assert(kPartChunk % kPartSub == 0, "a chunk is a whole number of sub-tiles");
@@ -273,10 +276,9 @@ __global__ __launch_bounds__(kPartBlock) void part_scan2_kernel(PartPlan P, Part
 __global__ __launch_bounds__(kPassBlock) void part_scatter_kernel(PartPass p) {
   __shared__ uint32_t sk[kPartSub];
   __shared__ uint32_t sv[kPartSub];
-  __shared__ uint16_t sd[kPartSub];
   __shared__ uint32_t cnt[kMaxFan];
   __shared__ uint32_t start[kMaxFan];
-  __shared__ unsigned long long run[kMaxFan];
+  __shared__ uint32_t run[kMaxFan];        // positions < 2^32 (n < 2^32 on this path)
   __shared__ uint32_t wt[kPassBlock / 64];
   uint32_t seg;
   uint64_t begin, end;
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(kPassBlock) void part_scatter_kernel(PartPass p) {
   unsigned long long* cur = p.level == 1 ? p.M.cursor1 : p.M.cursor2 + (uint64_t)seg * kFan2;
   for (uint32_t d = threadIdx.x; d < p.fan; d += kPassBlock) {
     const uint32_t c = h[d];
-    run[d] = c ? atomicAdd(&cur[d], (unsigned long long)c) : 0ull;
+    run[d] = c ? (uint32_t)atomicAdd(&cur[d], (unsigned long long)c) : 0u;
   }
   // Loads are branch-free (indices past the end re-read the last pair, and
   // those copies are never ranked), so the compiler can leave the next
@@ -326,7 +328,6 @@ __global__ __launch_bounds__(kPassBlock) void part_scatter_kernel(PartPass p) {
         const uint32_t pos = start[dig[j]] + rank[j];
         sk[pos] = k[j];
         sv[pos] = v[j];
-        sd[pos] = (uint16_t)dig[j];
       }
     }
     __syncthreads();
@@ -337,9 +338,10 @@ __global__ __launch_bounds__(kPassBlock) void part_scatter_kernel(PartPass p) {
     for (int j = 0; j < kPartPer; ++j) {
       const uint32_t i = j * kPassBlock + threadIdx.x;
       if (i < count) {
-        const uint32_t d = sd[i];
-        const uint64_t dst = run[d] + (i - start[d]);
-        p.out_k[dst] = sk[i];
+        const uint32_t key = sk[i];
+        const uint32_t d = part_digit(p.P, p.level, key);     // recomputed, not stored
+        const uint32_t dst = run[d] + (i - start[d]);
+        p.out_k[dst] = key;
         p.out_v[dst] = sv[i];
       }
     }
