@@ -759,7 +759,7 @@ def run_iceberg(args):
     for pct in ICEBERG_PERCENTS:
         t_keys = (b * pct) // 100
         table, failures = None, 0
-        for _ in range(5):
+        for _ in range(40):
             a, c = datagen.hash_constants(seed, 3)
             t = bht.Table(cap, b, "iht", a, c, rng_seed=datagen.rng_seed(seed), iht_threshold=t_keys)
             seed += 7919
@@ -775,9 +775,16 @@ def run_iceberg(args):
         ms = {k: [] for k in ("build", "find_pos", "find_neg", "find_mix",
                               "find_pos_early", "find_neg_early", "find_mix_early")}
         for step in range(args.warmup + args.steps):
-            if table.build(d_keys, d_vals) != bht.BHT_OK:
+            # near the scheme's limit a concurrent build can fail: retry with
+            # new constants (Section VII), counting the failures
+            while table.build(d_keys, d_vals) != bht.BHT_OK:
                 failures += 1
-                continue
+                if failures > 200:
+                    raise RuntimeError("iceberg %d%%: builds keep failing" % pct)
+                a, c = datagen.hash_constants(seed, 3)
+                seed += 7919
+                bht.bht_reseed(table.handle, bht.make_params(
+                    a, c, rng_seed=datagen.rng_seed(seed), iht_threshold=t_keys))
             rec = {"build": bht.bht_kernel_ms(table.handle)[0]}
             for early in (False, True):
                 bht.bht_set_tuning(table.handle, iht_early_exit=early)
@@ -792,7 +799,7 @@ def run_iceberg(args):
         st = bht.bht_build_counted(table.handle, d_keys, d_vals, total)
         probes = {"insert": int(total.item()) / n if st == bht.BHT_OK else None}
         tries = 0
-        while st != bht.BHT_OK and tries < 20:   # near the limit a build can fail: rebuild
+        while st != bht.BHT_OK and tries < 50:   # near the limit a build can fail: rebuild
             st = table.build(d_keys, d_vals)
             tries += 1
         if st != bht.BHT_OK:

@@ -42,7 +42,7 @@ namespace bht {
 #define BHT_PASS_BLOCK 1024
 #endif
 #ifndef BHT_PASS_PER
-#define BHT_PASS_PER 8
+#define BHT_PASS_PER 16
 #endif
 constexpr int kPartBlock = 256;                        // threads per scan block
 constexpr int kPassBlock = BHT_PASS_BLOCK;
