@@ -294,10 +294,20 @@ def run_schemes(args):
                  "buckets": table.info[0], "bucket_slots": b, "secondary_bucket_slots": b2,
                  "hashes": h, "key_bits": 64 if wide else 32}
         if not wide:
+            part, evicted, ovf_probes = bht.bht_build_stats(table.handle)
+            entry["build_path"] = "partitioned" if part else "concurrent"
+            if part:
+                entry["evicted_per_key"] = round(evicted / n, 5)
             # probe averages from the instrumented kernels (untimed runs)
             total = torch.zeros(1, dtype=torch.int64, device=dev)
-            bht.bht_build_counted(table.handle, d_keys, d_vals, total)
-            probes = {"insert": int(total.item()) / n}
+            st = bht.bht_build_counted(table.handle, d_keys, d_vals, total)
+            probes = {"insert": int(total.item()) / n if st == bht.BHT_OK else None}
+            tries = 0
+            while st != bht.BHT_OK and tries < 50:   # near the limit a build can fail
+                st = table.build(d_keys, d_vals)
+                tries += 1
+            if st != bht.BHT_OK:
+                raise RuntimeError("scheme %s: no rebuild after a failed counted build" % name)
             pr = torch.empty(n, dtype=torch.uint8, device=dev)
             for qname in ("find_pos", "find_neg", "find_mix"):
                 bht.bht_find_counted(table.handle, d_q[qname], out_v, out_f, pr, stream=stream)
@@ -310,7 +320,8 @@ def run_schemes(args):
             entry[k + "_gkeys_s"] = round(n / (avg * 1e-3) / 1e9, 4)
             if not wide:
                 p = entry["probes_per_key"]["insert" if k == "build" else k.replace("find_", "")]
-                entry["accesses_gps"][k] = round(p * n / (avg * 1e-3) / 1e9, 2)
+                if p is not None:
+                    entry["accesses_gps"][k] = round(p * n / (avg * 1e-3) / 1e9, 2)
         if scheme == "iht":
             # the early-exit find (a miss in a primary below t ends the query)
             bht.bht_set_tuning(table.handle, iht_early_exit=True)
