@@ -214,7 +214,7 @@ bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint6
  * bucket was full: the serial algorithm of Section III-A in one particular
  * insertion order, so layouts obey the same invariants.  It allocates a
  * library-owned workspace of about 8 bytes per pair on first use (kept
- * until bht_destroy).  BHT_BUILD_AUTO partitions builds of at least 2^20
+ * until bht_destroy).  BHT_BUILD_AUTO partitions builds of at least 2^18
  * pairs into tables whose memory the library owns (bht_create).
  * iht_early_exit (iceberg tables only, else UNSUPPORTED): 1 makes a find
  * stop after a miss in a primary bucket that holds fewer than

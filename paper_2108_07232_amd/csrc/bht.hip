@@ -349,7 +349,7 @@ Hash32 secondary_hash(const bht_table* t) {
 
 // Smallest build that takes the partitioned path by default: below it the
 // fixed cost of its eight launches outweighs the saved atomics.
-constexpr uint64_t kPartMinKeys = 1ull << 20;
+constexpr uint64_t kPartMinKeys = 1ull << 18;
 
 struct PartKernels {
   const void* place;
@@ -381,12 +381,18 @@ uint32_t log2_exact(uint64_t x) {
   return r;
 }
 
-// Bins, passes and digit counts for n pairs; false if the table has more
-// bins than two passes can address.
-bool part_plan(const bht_table* t, PartPlan* P) {
+// Bins, passes, digit counts and chunk size for n pairs; false if the table
+// has more bins than two passes can address.  Bins are as large as LDS
+// allows, halved (down to 32 buckets) while a single pass still covers them,
+// so small tables get enough bins to fill the device; chunks shrink for the
+// same reason.
+bool part_plan(const bht_table* t, uint64_t n, PartPlan* P) {
   const uint64_t S = t->b == 1 ? bin_slots<1>() : bin_slots<16>();
-  const uint64_t R = S / t->b;
+  uint64_t R = S / t->b;
+  while (R > 32 && (t->m + R / 2 - 1) / (R / 2) <= kMaxFan) R /= 2;
   const uint64_t nbins = (t->m + R - 1) / R;
+  const uint64_t per = (n + (uint64_t)kPartSub * 512 - 1) / ((uint64_t)kPartSub * 512);
+  P->chunk = kPartSub * (uint32_t)std::min<uint64_t>(std::max<uint64_t>(per, 1), kPartChunkMax / kPartSub);
   P->H = make_hash32(t->params, t->m, t->params.num_hashes);
   P->bin_shift = log2_exact(R);
   P->nbins = (uint32_t)nbins;
@@ -417,8 +423,8 @@ PartLayout part_layout(const PartPlan& P, uint64_t n) {
     off += (bytes + 255) / 256 * 256;
     return at;
   };
-  L.chunks1 = (n + kPartChunk - 1) / kPartChunk;
-  L.chunks2 = P.levels == 2 ? n / kPartChunk + P.fan1 : 0;
+  L.chunks1 = (n + P.chunk - 1) / P.chunk;
+  L.chunks2 = P.levels == 2 ? n / P.chunk + P.fan1 : 0;
   L.hist1 = take(L.chunks1 * P.fan1 * 4);
   L.hist2 = take(L.chunks2 * kFan2 * 4);
   L.total1 = take(P.fan1 * 8ull);
@@ -443,7 +449,7 @@ bool use_partitioned(const bht_table* t, uint64_t n, bool counting) {
   if (t->scheme != BHT_BCHT && t->scheme != BHT_CHT1) return false;
   if (t->build_mode == BHT_BUILD_CONCURRENT) return false;
   PartPlan P;
-  if (!part_plan(t, &P)) return false;
+  if (!part_plan(t, n, &P)) return false;
   if (t->build_mode == BHT_BUILD_PARTITIONED) return true;
   return n >= kPartMinKeys && t->owns_memory;
 }
@@ -451,7 +457,7 @@ bool use_partitioned(const bht_table* t, uint64_t n, bool counting) {
 bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_t* vals,
                                uint64_t n, hipStream_t st) {
   PartPlan P;
-  if (!part_plan(t, &P)) return fail(BHT_ERR_UNSUPPORTED, "table too large to partition");
+  if (!part_plan(t, n, &P)) return fail(BHT_ERR_UNSUPPORTED, "table too large to partition");
   PartKernels K;
   if (!part_kernels(t->b, t->tile, &K))
     return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");

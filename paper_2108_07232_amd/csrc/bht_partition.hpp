@@ -9,10 +9,11 @@
 //
 //   1. partition: the pairs are grouped by the region of their first
 //      bucket H_0(k) (a bin of R consecutive buckets whose slots fit in
-//      LDS), with one or two radix passes (fan-out at most 1024, then 256);
-//      each pass counts digits per chunk of 65,536 pairs, reserves output
-//      ranges per (chunk, digit), and writes each 4,096-pair sub-tile in
-//      digit order staged through LDS, so stores are contiguous runs;
+//      LDS; smaller bins for small tables, so that there are enough of
+//      them to fill the device), with one or two radix passes (fan-out at
+//      most 1024, then 256); each pass counts digits per chunk of pairs,
+//      reserves output ranges per (chunk, digit), and writes each sub-tile
+//      in digit order staged through LDS, so stores are contiguous runs;
 //   2. bin placement: one workgroup per bin builds its buckets in LDS,
 //      placing each pair in its first bucket at the next free slot
 //      (a local atomic on the bucket's load); a pair that finds its first
@@ -48,8 +49,7 @@ constexpr int kPartBlock = 256;                        // threads per scan block
 constexpr int kPassBlock = BHT_PASS_BLOCK;
 constexpr int kPartSub = BHT_PASS_PER * kPassBlock;
 constexpr int kPartPer = kPartSub / kPassBlock;        // pairs per thread per sub-tile
-constexpr uint32_t kPartChunk = 65536;                 // pairs per partition block
-static_assert(kPartChunk % kPartSub == 0, "a chunk is a whole number of sub-tiles");
+constexpr uint32_t kPartChunkMax = 4 * kPartSub;       // pairs per partition block, at most
 constexpr uint32_t kMaxFan = 1024;                     // digits of the first pass, at most
 constexpr uint32_t kFan2 = 256;                        // digits of the second pass
 constexpr int kBinBlock = 512;                         // threads per bin placement block
@@ -62,10 +62,11 @@ constexpr int bin_slots() { return B == 1 ? 4096 : 8192; }
 
 struct PartPlan {
   Hash32 H;             // first hash (index 0) and bucket count
-  uint32_t bin_shift;   // bin = H_0(k) >> bin_shift
+  uint32_t bin_shift;   // bin = H_0(k) >> bin_shift: 2^bin_shift buckets per bin
   uint32_t levels;      // radix passes: 1 or 2
   uint32_t fan1;        // digits of the first pass
   uint32_t nbins;
+  uint32_t chunk;       // pairs per partition block (a multiple of the sub-tile)
 };
 
 // Device metadata of one partitioned build (one allocation, see the host).
@@ -110,12 +111,13 @@ __device__ __forceinline__ uint32_t part_digit(const PartPlan& P, uint32_t level
 // block has no chunk (the second pass launches an upper bound of blocks).
 __device__ __forceinline__ bool part_chunk(const PartPass& p, uint32_t blk, uint32_t* seg,
                                            uint64_t* begin, uint64_t* end) {
+  const uint64_t C = p.P.chunk;
   if (p.level == 1) {
-    const uint64_t b = (uint64_t)blk * kPartChunk;
+    const uint64_t b = (uint64_t)blk * C;
     if (b >= p.n) return false;
     *seg = 0;
     *begin = b;
-    *end = b + kPartChunk < p.n ? b + kPartChunk : p.n;
+    *end = b + C < p.n ? b + C : p.n;
     return true;
   }
   const uint32_t* cf = p.M.chunk_first;
@@ -127,10 +129,10 @@ __device__ __forceinline__ bool part_chunk(const PartPass& p, uint32_t blk, uint
     else hi = mid;
   }
   const uint64_t s0 = p.M.seg_start[lo], s1 = s0 + p.M.seg_len[lo];
-  const uint64_t b = s0 + (uint64_t)(blk - cf[lo]) * kPartChunk;
+  const uint64_t b = s0 + (uint64_t)(blk - cf[lo]) * C;
   *seg = lo;
   *begin = b;
-  *end = b + kPartChunk < s1 ? b + kPartChunk : s1;
+  *end = b + C < s1 ? b + C : s1;
   return true;
 }
 
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(kPartBlock) void part_scan1_kernel(PartPlan P, Part
     } else {
       M.seg_start[d] = base[d];
       M.seg_len[d] = c;
-      chunks[d] = (c + kPartChunk - 1) / kPartChunk;
+      chunks[d] = (c + P.chunk - 1) / P.chunk;
     }
   }
   if (P.levels == 1) return;          // uniform
@@ -377,17 +379,18 @@ struct BinArgs {
 template <int B>
 __global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
   constexpr int S = bin_slots<B>();
-  constexpr int R = S / B;                       // buckets per bin
+  constexpr int RMAX = S / B;                    // buckets per bin, at most
   __shared__ u64x2 tbl2[S / 2];
-  __shared__ uint32_t load[R];
+  __shared__ uint32_t load[RMAX];
   __shared__ uint32_t ovf;
   unsigned long long* tbl = reinterpret_cast<unsigned long long*>(tbl2);
+  const uint32_t R = 1u << a.P.bin_shift;        // buckets per bin of this plan (<= RMAX)
   const uint32_t bin = blockIdx.x;
   const uint64_t first = (uint64_t)bin * R;
   const uint32_t nb = (uint64_t)a.P.H.m - first < (uint64_t)R ? (uint32_t)(a.P.H.m - first) : R;
   const u64x2 e2 = {kEmptyPair, kEmptyPair};
-  for (int i = threadIdx.x; i < S / 2; i += kBinBlock) tbl2[i] = e2;
-  for (int i = threadIdx.x; i < R; i += kBinBlock) load[i] = 0;
+  for (uint32_t i = threadIdx.x; i < (R * B + 1) / 2; i += kBinBlock) tbl2[i] = e2;
+  for (uint32_t i = threadIdx.x; i < R; i += kBinBlock) load[i] = 0;
   if (threadIdx.x == 0) ovf = 0;
   uint32_t rng = a.rng_seed ^ (bin * 0x9E3779B9u) ^ (threadIdx.x * 0x85EBCA6Bu);
   if (rng == 0) rng = 0x2545F491u;
