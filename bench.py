@@ -556,7 +556,9 @@ def run_serve(args):
             for r in reqs:
                 r.done, r.status, r.launch = -1.0, -1, -1
             if mode == "continuous":
-                srv = serve.Server(torch, int(args.budget_gb * 1e9))
+                # build workspaces sized for the largest build of the stream (2^24 pairs)
+                srv = serve.Server(torch, int(args.budget_gb * 1e9),
+                                   workspace_bytes=8 * (1 << 24) + (16 << 20))
                 wk = torch.arange(1, 257, dtype=torch.int32, device="cuda")
                 srv.warmup(wk, wk)
                 for tid, t in enumerate(tables):

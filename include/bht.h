@@ -173,6 +173,25 @@ bht_status bht_build_retry(bht_table* t, const void* d_keys, const void* d_value
 bht_status bht_build_stats(const bht_table* t, uint32_t* partitioned, uint64_t* evicted,
                            uint64_t* overflow_probes);
 
+/* Bytes of caller-owned workspace a partitioned build of n pairs into this
+ * table needs (see bht_tuning's build_mode), or 0 when the table does not
+ * take that path (schemes other than BCHT and CHT1, 64-bit keys, n = 0,
+ * n >= 2^32, n above the slot count). */
+uint64_t bht_build_workspace_bytes(const bht_table* t, uint64_t n);
+
+/* As bht_build_async, but a BCHT or CHT1 build takes the partitioned path
+ * with the caller's device workspace d_workspace (workspace_bytes >=
+ * bht_build_workspace_bytes(t, n), 256-byte aligned) instead of allocating
+ * one, so a serving loop can keep one workspace per stream and never
+ * allocate while building.  The workspace must stay untouched until
+ * bht_build_wait returns.  Tables the partitioned path does not apply to
+ * (or build_mode = BHT_BUILD_CONCURRENT) are built with the concurrent
+ * kernel and the workspace is not used.  INVALID_ARG for a null, too small
+ * or misaligned workspace. */
+bht_status bht_build_async_in(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,
+                              uint64_t n, void* d_workspace, uint64_t workspace_bytes,
+                              void* stream);
+
 /* Bulk find of n queries (Section III; Section V).  d_out_values[i] is the
  * value stored with d_queries[i], or 0xFFFFFFFF when absent; d_out_found[i]
  * is 1 when present, else 0.  Asynchronous on stream; the table must be

@@ -90,6 +90,8 @@ _SIGS = {
     "bht_build64": (_st, [_p, _p, _p, _u64, _p]),
     "bht_find64": (_st, [_p, _p, _u64, _p, _p, _p]),
     "bht_build_counted": (_st, [_p, _p, _p, _u64, _p, _p]),
+    "bht_build_workspace_bytes": (_u64, [_p, _u64]),
+    "bht_build_async_in": (_st, [_p, _p, _p, _u64, _p, _u64, _p]),
     "bht_build_stats": (_st, [_p, ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "bht_params_from_seed": (_st, [_u64, ctypes.c_int, _u32, ctypes.POINTER(bht_params)]),
     "bht_build_retry": (_st, [_p, _p, _p, _u64, _u64, _u32, ctypes.POINTER(_u32), _p]),
@@ -222,6 +224,20 @@ def bht_build_async(table, keys, values, n=None, stream=None):
     n = keys.numel() if n is None else n
     _check(_lib.bht_build_async(table, _dptr(keys, None, "keys"), _dptr(values, None, "values"),
                                 n, _stream(stream)), "bht_build_async")
+
+
+def bht_build_workspace_bytes(table, n: int) -> int:
+    return int(_lib.bht_build_workspace_bytes(table, n))
+
+
+def bht_build_async_in(table, keys, values, workspace, n=None, stream=None):
+    """Enqueues a build using the caller's device workspace (a uint8 tensor
+    of at least bht_build_workspace_bytes(table, n) bytes)."""
+    n = keys.numel() if n is None else n
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(_lib.bht_build_async_in(table, _dptr(keys, None, "keys"), _dptr(values, None, "values"),
+                                   n, _dptr(workspace, None, "workspace"), nbytes, _stream(stream)),
+           "bht_build_async_in")
 
 
 def bht_build_wait(table, stream=None) -> int:

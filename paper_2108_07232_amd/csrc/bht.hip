@@ -454,15 +454,20 @@ bool use_partitioned(const bht_table* t, uint64_t n, bool counting) {
   return n >= kPartMinKeys && t->owns_memory;
 }
 
+// ws: caller-owned workspace of ws_bytes, or null for the table's own
+// (allocated on first use and grown as needed).
 bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_t* vals,
-                               uint64_t n, hipStream_t st) {
+                               uint64_t n, hipStream_t st, void* ws = nullptr,
+                               uint64_t ws_bytes = 0) {
   PartPlan P;
   if (!part_plan(t, n, &P)) return fail(BHT_ERR_UNSUPPORTED, "table too large to partition");
   PartKernels K;
   if (!part_kernels(t->b, t->tile, &K))
     return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
   const PartLayout L = part_layout(P, n);
-  if (t->part_bytes < L.bytes) {
+  if (ws && (ws_bytes < L.bytes || (reinterpret_cast<uintptr_t>(ws) & 255)))
+    return fail(BHT_ERR_INVALID_ARG, "workspace too small or not 256-byte aligned");
+  if (!ws && t->part_bytes < L.bytes) {
     // grow the workspace; the stream's earlier work may still use the old one
     if (t->d_part) {
       HIP_TRY(hipStreamSynchronize(st));
@@ -477,7 +482,7 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
     }
     t->part_bytes = L.bytes;
   }
-  char* w = static_cast<char*>(t->d_part);
+  char* w = static_cast<char*>(ws ? ws : t->d_part);
   PartMeta M;
   M.hist1 = reinterpret_cast<uint32_t*>(w + L.hist1);
   M.hist2 = reinterpret_cast<uint32_t*>(w + L.hist2);
@@ -813,6 +818,33 @@ bht_status bht_reseed(bht_table* t, const bht_params* params) {
 bht_status bht_build_async(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,
                            uint64_t n, void* stream) {
   return build32_enqueue(t, d_keys, d_values, n, nullptr, stream);
+}
+
+uint64_t bht_build_workspace_bytes(const bht_table* t, uint64_t n) {
+  if (!t || t->key_bits != 32 || n == 0 || n >= (1ull << 32) || n > t->slots) return 0;
+  if (t->scheme != BHT_BCHT && t->scheme != BHT_CHT1) return 0;
+  PartPlan P;
+  if (!part_plan(t, n, &P)) return 0;
+  return part_layout(P, n).bytes;
+}
+
+bht_status bht_build_async_in(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,
+                              uint64_t n, void* d_workspace, uint64_t workspace_bytes,
+                              void* stream) {
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  if (t->key_bits != 32) return fail(BHT_ERR_INVALID_ARG, "table holds 64-bit keys");
+  if (n > t->slots) return fail(BHT_ERR_CAPACITY, "more pairs than slots");
+  if (n && (!d_keys || !d_values)) return fail(BHT_ERR_INVALID_ARG, "null key or value pointer");
+  if (!d_workspace) return fail(BHT_ERR_INVALID_ARG, "null workspace");
+  if (bht_build_workspace_bytes(t, n) == 0 || t->build_mode == BHT_BUILD_CONCURRENT)
+    return build32_enqueue(t, d_keys, d_values, n, nullptr, stream);    // workspace unused
+  KernelSet ks;
+  if (!pick(t, t->tile, t->find_schedule, false, &ks))
+    return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
+  t->built = false;
+  t->pending_partitioned = false;
+  return build32_partitioned(t, d_keys, d_values, n, as_stream(stream), d_workspace,
+                             workspace_bytes);
 }
 
 bht_status bht_build_wait(bht_table* t, void* stream) {

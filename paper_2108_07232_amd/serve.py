@@ -12,7 +12,7 @@ Completion is observed with events; a request's latency runs from its
 arrival to the end of the launch that answered it.
 
 Host-side orchestration only: building and querying run in the library's
-kernels (bht_build_async / bht_multi_find).
+kernels (bht_build_async_in with a per-stream workspace, bht_multi_find).
 """
 from __future__ import annotations
 
@@ -51,6 +51,7 @@ class _Slot:
     requests: list = field(default_factory=list)
     kind: str = ""
     done_event: object = None       # reused for every launch of this slot
+    workspace: object = None        # build slots: device workspace of the partitioned build
 
 
 class Server:
@@ -58,7 +59,7 @@ class Server:
 
     def __init__(self, torch, budget_bytes: int, streams: int = 4, build_streams: int = 2,
                  max_batch: int = 1024, max_items: int = 1 << 16, item_size: int = 4096,
-                 bucket: int = 16):
+                 bucket: int = 16, workspace_bytes: int = 0):
         self.torch = torch
         self.budget = budget_bytes
         self.bucket = bucket
@@ -75,6 +76,11 @@ class Server:
         self.build_slots = [_Slot(torch.cuda.Stream(), None) for _ in range(build_streams)]
         for slot in self.lookup_slots + self.build_slots:
             slot.done_event = torch.cuda.Event()
+        # one build workspace per build stream (reused: a slot runs one build
+        # at a time), so builds never allocate in the loop; grown on demand
+        for slot in self.build_slots:
+            if workspace_bytes:
+                slot.workspace = torch.empty(workspace_bytes, dtype=torch.uint8, device="cuda")
         self.building = set()                        # ids with a build waiting or running
 
     def close(self):
@@ -97,7 +103,7 @@ class Server:
                 buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
                 t = bht.Table(4 * keys.numel(), self.bucket, "bcht", [3, 5, 7], [11, 13, 17],
                               buffer=buf)
-                bht.bht_build_async(t.handle, keys, vals, stream=slot.stream)
+                self._build(slot, t, keys, vals)
                 bht.bht_build_wait(t.handle, stream=slot.stream)
                 for ls in self.lookup_slots:
                     ov = torch.empty(keys.numel(), dtype=torch.int32, device="cuda")
@@ -107,6 +113,17 @@ class Server:
                     ls.stream.synchronize()
                 t.close()
         torch.cuda.synchronize()
+
+    def _build(self, slot, table, keys, vals):
+        """Enqueues a build on the slot's stream, through the partitioned
+        path with the slot's workspace when the table takes it."""
+        need = bht.bht_build_workspace_bytes(table.handle, keys.numel())
+        if need == 0:
+            bht.bht_build_async(table.handle, keys, vals, stream=slot.stream)
+            return
+        if slot.workspace is None or slot.workspace.numel() < need:
+            slot.workspace = self.torch.empty(need, dtype=self.torch.uint8, device="cuda")
+        bht.bht_build_async_in(table.handle, keys, vals, slot.workspace, stream=slot.stream)
 
     # ------------------------------------------------------------- tables
 
@@ -202,7 +219,7 @@ class Server:
                                           rng_seed=r.rng_seed, buffer=buf)
                         self.tables[r.table] = table
                         self.bytes += table.info[3]
-                        bht.bht_build_async(table.handle, r.keys, r.vals, stream=slot.stream)
+                        self._build(slot, table, r.keys, r.vals)
                         slot.done_event.record(slot.stream)
                     slot.event, slot.requests, slot.kind = slot.done_event, [r], "build"
                     r.launch = self.launches

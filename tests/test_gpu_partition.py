@@ -201,3 +201,38 @@ def test_eviction_count_equals_first_bucket_overflow(b, n, lf):
     assert st == B.BHT_OK
     assert B.bht_build_stats(t.handle) == (False, 0, 0)
     t.close()
+
+
+def test_build_with_caller_workspace():
+    """bht_build_async_in takes the partitioned path with caller-owned
+    workspace (here on a table in caller-owned memory too): the layout is
+    valid, lookups equal brute force, a too-small workspace is refused, and
+    schemes without that path report a size of 0 and build normally."""
+    import torch
+    B = bht()
+    n = 300007
+    keys, vals = workload(n, 41)
+    params = oracle.params_for("bcht", n, 0.9, 1100)
+    pb = B.make_params(params.a, params.c, rng_seed=params.rng_seed)
+    nbytes = B.bht_table_bytes(params.m * 16, 16, "bcht", pb)
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    t = B.Table(params.m * 16, 16, "bcht", params.a, params.c, rng_seed=params.rng_seed, buffer=buf)
+    need = B.bht_build_workspace_bytes(t.handle, n)
+    assert need > 8 * n
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    dk, dv = dev(keys), dev(vals)
+    with pytest.raises(B.BhtError) as e:
+        B.bht_build_async_in(t.handle, dk, dv, ws[:need - 256])
+    assert e.value.status == B.BHT_ERR_INVALID_ARG
+    B.bht_build_async_in(t.handle, dk, dv, ws)
+    assert B.bht_build_wait(t.handle) == B.BHT_OK
+    assert B.bht_build_stats(t.handle)[0]
+    check_table(t, params, keys, vals)
+    t.close()
+    p2 = oracle.params_for("bp2ht", n, 0.8, 1101)
+    t = B.Table(p2.m * 16, 16, "bp2ht", p2.a, p2.c)
+    assert B.bht_build_workspace_bytes(t.handle, n) == 0
+    B.bht_build_async_in(t.handle, dk, dv, ws)
+    assert B.bht_build_wait(t.handle) == B.BHT_OK
+    assert oracle.check32(p2, t.download(), keys, vals)[0] == 0
+    t.close()
