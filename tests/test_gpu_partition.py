@@ -236,3 +236,34 @@ def test_build_with_caller_workspace():
     assert B.bht_build_wait(t.handle) == B.BHT_OK
     assert oracle.check32(p2, t.download(), keys, vals)[0] == 0
     t.close()
+
+
+@pytest.mark.parametrize("scheme,b,n,cap", [
+    ("bcht", 16, 1, 16), ("bcht", 16, 17, 32), ("bcht", 16, 500, 600), ("bcht", 4, 1000, 1200),
+    ("bcht", 32, 5000, 6000), ("bcht", 8, 1 << 18, 300000), ("cht1", 1, 700, 1000),
+    ("bcht", 16, (1 << 18) - 1, 300000), ("bcht", 16, 1 << 18, 300000),
+])
+def test_partitioned_build_edge_sizes(scheme, b, n, cap):
+    """Tiny tables (one bucket, fewer buckets than a minimum bin), sizes at
+    the default threshold, every bucket size: layouts valid, lookups exact,
+    and both build modes answer alike."""
+    import torch
+    B = bht()
+    keys, vals = workload(n, 71)
+    h = 3
+    for s in range(10):
+        a, c = datagen.hash_constants(7100 + s, h)
+        params = oracle.Params(scheme=scheme, b=b, m=-(-cap // b), h=h, a=a, c=c,
+                               rng_seed=datagen.rng_seed(7100 + s))
+        t, st = build_partitioned(params, keys, vals)
+        if st == B.BHT_OK:
+            break
+        t.close()
+    else:
+        pytest.fail("no partitioned build succeeded")
+    check_table(t, params, keys, vals, n_queries=max(2 * n, 64))
+    t.close()
+    t, st = build_partitioned(params, keys, vals, mode="auto")
+    if st == B.BHT_OK:
+        check_table(t, params, keys, vals, n_queries=max(2 * n, 64))
+    t.close()
