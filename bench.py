@@ -398,14 +398,14 @@ def run_batched(args):
                           queries=d_q[sl], out_v=out_v[sl], out_f=out_f[sl]))
     sample = specs[::8]
     best, table = autotune.tune(bht, torch, sample, reps=3, log=log)
-    b, w, item = best
-    log("autotuner choice: bucket %d, tile %d, item %d" % best)
-    sec, sts = autotune.time_batch(bht, torch, specs, b, w, item, reps=args.steps)
+    b, w, item, unroll = best
+    log("autotuner choice: bucket %d, tile %d, item %d, unroll %d" % best)
+    sec, sts = autotune.time_batch(bht, torch, specs, b, w, item, unroll=unroll, reps=args.steps)
     failed = sum(1 for s in sts if s != bht.BHT_OK)
     found = int(out_f.sum(dtype=torch.int64).item())
     # plain per-table calls with the same configuration
-    tables = [bht.Table(s["capacity"], b, "bcht", s["a"], s["c"], rng_seed=s["rng_seed"], tile=w)
-              for s in specs]
+    tables = [bht.Table(s["capacity"], b, "bcht", s["a"], s["c"], rng_seed=s["rng_seed"], tile=w,
+                        query_unroll=unroll) for s in specs]
     stream = torch.cuda.current_stream()
 
     def plain():
@@ -430,9 +430,9 @@ def run_batched(args):
     line = json.dumps({
         "workload": "batched", "tables": count, "keys": total, "queries": total,
         "key_range_log2": [10, 22], "load_factor": 0.9, "positive_fraction": 0.5,
-        "autotune": {"choice": {"bucket": b, "tile": w, "item": item},
+        "autotune": {"choice": {"bucket": b, "tile": w, "item": item, "unroll": unroll},
                      "sample_tables": len(sample),
-                     "ms": {"b%d_w%d_i%d" % k: round(v * 1e3, 3) for k, v in table.items()}},
+                     "ms": {"b%d_w%d_i%d_u%d" % k: round(v * 1e3, 3) for k, v in table.items()}},
         "batched": {"seconds": round(sec, 5), "gops_s": round(ops / sec / 1e9, 3),
                     "failed_tables": failed, "found": found},
         "plain_per_table": {"seconds": round(plain_sec, 5), "gops_s": round(ops / plain_sec / 1e9, 3)},

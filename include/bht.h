@@ -240,7 +240,9 @@ bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint6
  * iht_threshold keys, which proves absence because a key goes to a
  * secondary bucket only once its primary holds that many (Section III-C);
  * such a negative query costs one probe instead of three.  0 (default)
- * probes every candidate, as Section V-D describes. */
+ * probes every candidate, as Section V-D describes.  query_unroll (chunk
+ * schedule, single-table and batched queries): queries per lane per chunk,
+ * 1 (0 = 1) or 2; the autotuner of the batched mode chooses it. */
 typedef enum {
   BHT_FIND_DEFAULT = 0,
   BHT_FIND_REFILL = 1,
@@ -258,6 +260,7 @@ typedef struct {
   uint32_t grid_blocks;
   uint32_t build_mode;
   uint32_t iht_early_exit;
+  uint32_t query_unroll;
 } bht_tuning;
 bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning);
 bht_status bht_get_tuning(const bht_table* t, bht_tuning* tuning);
@@ -302,7 +305,8 @@ bht_status bht_diag_cas(void* d_buf, uint64_t bytes, uint64_t n_ops, uint64_t se
 
 /* Batched mode (not in the paper): many bucketed cuckoo tables of uneven
  * sizes built and then queried together.  Every table of a batch is a
- * 32-bit BHT_BCHT table with the same bucket size and tile width.  Entry i
+ * 32-bit BHT_BCHT table with the same bucket size, tile width and query
+ * unroll (bht_tuning).  Entry i
  * names its table, its n_keys input pairs and its n_queries queries with
  * their output arrays (all caller-owned device memory, as for bht_build and
  * bht_find).  bht_batch_create copies the table descriptors and the work

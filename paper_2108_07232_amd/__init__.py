@@ -49,7 +49,7 @@ class bht_params(ctypes.Structure):
 class bht_tuning(ctypes.Structure):
     _fields_ = [("tile_width", ctypes.c_uint32), ("find_schedule", ctypes.c_uint32),
                 ("grid_blocks", ctypes.c_uint32), ("build_mode", ctypes.c_uint32),
-                ("iht_early_exit", ctypes.c_uint32)]
+                ("iht_early_exit", ctypes.c_uint32), ("query_unroll", ctypes.c_uint32)]
 
 
 class bht_batch_entry(ctypes.Structure):
@@ -318,19 +318,21 @@ def bht_find_counted(table, queries, out_values, out_found, probes, n=None, stre
 
 
 def bht_set_tuning(table, tile_width: int = 0, find_schedule=0, grid_blocks: int = 0,
-                   build_mode=0, iht_early_exit: bool = False):
+                   build_mode=0, iht_early_exit: bool = False, query_unroll: int = 0):
     if isinstance(find_schedule, str):
         find_schedule = FIND_SCHEDULES[find_schedule]
     if isinstance(build_mode, str):
         build_mode = BUILD_MODES[build_mode]
-    tu = bht_tuning(tile_width, find_schedule, grid_blocks, build_mode, int(bool(iht_early_exit)))
+    tu = bht_tuning(tile_width, find_schedule, grid_blocks, build_mode, int(bool(iht_early_exit)),
+                    query_unroll)
     _check(_lib.bht_set_tuning(table, ctypes.byref(tu)), "bht_set_tuning")
 
 
 def bht_get_tuning(table):
     tu = bht_tuning()
     _check(_lib.bht_get_tuning(table, ctypes.byref(tu)), "bht_get_tuning")
-    return tu.tile_width, tu.find_schedule, tu.grid_blocks, tu.build_mode, tu.iht_early_exit
+    return (tu.tile_width, tu.find_schedule, tu.grid_blocks, tu.build_mode, tu.iht_early_exit,
+            tu.query_unroll)
 
 
 def bht_enable_timing(table, on: bool = True):
@@ -467,7 +469,8 @@ class Table:
     def __init__(self, capacity_slots: int, bucket_size: int, scheme="bcht", a=(), b=(),
                  key_bits=32, rng_seed=0x9E3779B9, max_chain=128, iht_threshold=0,
                  iht_secondary_b=0, iht_secondary_m=0, tile=None, find_schedule=0,
-                 grid_blocks=0, buffer=None, build_mode=0, iht_early_exit=False):
+                 grid_blocks=0, buffer=None, build_mode=0, iht_early_exit=False,
+                 query_unroll=0):
         self.params = make_params(a, b, key_bits=key_bits, rng_seed=rng_seed,
                                   max_chain=max_chain, iht_threshold=iht_threshold,
                                   iht_secondary_b=iht_secondary_b,
@@ -478,9 +481,10 @@ class Table:
             self.handle = bht_create(capacity_slots, bucket_size, scheme, self.params)
         else:
             self.handle = bht_create_in(capacity_slots, bucket_size, scheme, self.params, buffer)
-        if tile is not None or find_schedule or grid_blocks or build_mode or iht_early_exit:
+        if (tile is not None or find_schedule or grid_blocks or build_mode or iht_early_exit
+                or query_unroll):
             bht_set_tuning(self.handle, tile or 0, find_schedule, grid_blocks, build_mode,
-                           iht_early_exit)
+                           iht_early_exit, query_unroll)
 
     def close(self):
         if self.handle:

@@ -1,5 +1,6 @@
-"""Autotuner for batched mode: picks bucket size, tile width and work-item
-size for a batch of tables by timing each candidate on the device.
+"""Autotuner for batched mode: picks bucket size, tile width, work-item size
+and query unroll (queries per lane per chunk) for a batch of tables by
+timing each candidate on the device.
 
 It only orchestrates calls of the C ABI (tables are created per candidate,
 because the bucket size changes their geometry); every build and query runs
@@ -14,23 +15,27 @@ import time
 BUCKETS = (8, 16, 32)
 TILES = (4, 8, 16)
 ITEMS = (2048, 8192)
+UNROLLS = (1, 2)
 
 
-def candidates(buckets=BUCKETS, tiles=TILES, items=ITEMS):
-    """(bucket size, tile width, item size) triples the library has kernels for."""
+def candidates(buckets=BUCKETS, tiles=TILES, items=ITEMS, unrolls=UNROLLS):
+    """(bucket size, tile width, item size, query unroll) the library has
+    kernels for."""
     supported = {(8, 4), (8, 8), (16, 4), (16, 8), (16, 16), (32, 8), (32, 16)}
-    return [(b, w, it) for b, w, it in itertools.product(buckets, tiles, items)
+    return [(b, w, it, u) for b, w, it, u in itertools.product(buckets, tiles, items, unrolls)
             if (b, w) in supported]
 
 
-def time_batch(bht, torch, specs, b, w, item, reps=3, stream=None):
+def time_batch(bht, torch, specs, b, w, item, unroll=1, reps=3, stream=None):
     """Median seconds of one batched build + query pass over the tables in
     `specs` (dicts with capacity, hash constants, device inputs and outputs),
-    built with bucket size b and tile width w.  Returns (seconds, statuses)."""
+    built with bucket size b, tile width w and query unroll.  Returns
+    (seconds, statuses)."""
     tables = []
     try:
         for s in specs:
-            t = bht.Table(s["capacity"], b, "bcht", s["a"], s["c"], rng_seed=s["rng_seed"], tile=w)
+            t = bht.Table(s["capacity"], b, "bcht", s["a"], s["c"], rng_seed=s["rng_seed"], tile=w,
+                          query_unroll=unroll)
             tables.append(t)
         entries = [(t.handle, s["keys"], s["vals"], s["queries"], s["out_v"], s["out_f"])
                    for t, s in zip(tables, specs)]
@@ -61,12 +66,12 @@ def tune(bht, torch, specs, cands=None, reps=3, log=None):
     {candidate: seconds})."""
     cands = cands or candidates()
     results = {}
-    for b, w, item in cands:
-        sec, sts = time_batch(bht, torch, specs, b, w, item, reps=reps)
+    for b, w, item, unroll in cands:
+        sec, sts = time_batch(bht, torch, specs, b, w, item, unroll=unroll, reps=reps)
         if sts is not None and any(s != bht.BHT_OK for s in sts):
             sec = float("inf")       # a configuration that cannot build every table loses
-        results[(b, w, item)] = sec
+        results[(b, w, item, unroll)] = sec
         if log:
-            log("autotune b=%d tile=%d item=%d: %.3f ms" % (b, w, item, sec * 1e3))
+            log("autotune b=%d tile=%d item=%d unroll=%d: %.3f ms" % (b, w, item, unroll, sec * 1e3))
     best = min(results, key=results.get)
     return best, results

@@ -46,6 +46,7 @@ struct bht_table {
   bool build_timed, find_timed;
   uint32_t build_mode;     // bht_build_mode
   uint32_t iht_early_exit; // iceberg finds stop after a primary below the threshold
+  uint32_t unroll;         // chunk-schedule queries per lane per chunk (0 = 1)
   void* d_part;            // partitioned build workspace (library-owned)
   uint64_t part_bytes;
   bool pending_partitioned;
@@ -258,11 +259,13 @@ struct KernelSet {
 constexpr uint32_t kDefaultSchedule = BHT_FIND_CHUNK;
 
 template <int B, int W, bool C>
-KernelSet cuckoo_set(uint32_t schedule) {
+KernelSet cuckoo_set(uint32_t schedule, uint32_t unroll) {
   const bool chunk = schedule == BHT_FIND_CHUNK || schedule == BHT_FIND_PARALLEL;
+  const void* chunk_kernel = unroll == 2 ? (const void*)cuckoo_find_chunk_kernel<B, W, C, 2>
+                                         : (const void*)cuckoo_find_chunk_kernel<B, W, C, 1>;
   return {Kind::Cuckoo, (const void*)cuckoo_build_kernel<B, W, C>,
           schedule == BHT_FIND_PARALLEL ? (const void*)cuckoo_find_parallel_kernel<B, W, C>
-          : chunk                       ? (const void*)cuckoo_find_chunk_kernel<B, W, C>
+          : chunk                       ? chunk_kernel
                                         : (const void*)cuckoo_find_kernel<B, W, C>,
           chunk};
 }
@@ -287,10 +290,10 @@ KernelSet iceberg_set() {
 
 template <bool C>
 bool pick_t(bht_scheme scheme, uint32_t b, uint32_t b2, uint32_t w, uint32_t schedule,
-            KernelSet* ks) {
+            uint32_t unroll, KernelSet* ks) {
   if (scheme == BHT_BCHT || scheme == BHT_CHT1) {
 #define BHT_CASE(B_, W_) \
-  if (b == B_ && w == W_) return *ks = cuckoo_set<B_, W_, C>(schedule), true;
+  if (b == B_ && w == W_) return *ks = cuckoo_set<B_, W_, C>(schedule, unroll), true;
     BHT_CASE(1, 1)
     BHT_CASE(4, 4)
     BHT_CASE(8, 4)
@@ -323,8 +326,8 @@ bool pick_t(bht_scheme scheme, uint32_t b, uint32_t b2, uint32_t w, uint32_t sch
 bool pick(const bht_table* t, uint32_t w, uint32_t schedule, bool count, KernelSet* ks) {
   if (schedule == BHT_FIND_DEFAULT) schedule = kDefaultSchedule;
   const uint32_t b2 = t->scheme == BHT_IHT ? t->params.iht_secondary_b : 0;
-  return count ? pick_t<true>(t->scheme, t->b, b2, w, schedule, ks)
-               : pick_t<false>(t->scheme, t->b, b2, w, schedule, ks);
+  return count ? pick_t<true>(t->scheme, t->b, b2, w, schedule, t->unroll, ks)
+               : pick_t<false>(t->scheme, t->b, b2, w, schedule, t->unroll, ks);
 }
 
 bht_status launch_fill(bht_table* t, hipStream_t st) {
@@ -1014,6 +1017,7 @@ bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning) {
   if (tuning->find_schedule > BHT_FIND_PARALLEL) return fail(BHT_ERR_INVALID_ARG, "bad schedule");
   if (tuning->build_mode > BHT_BUILD_PARTITIONED) return fail(BHT_ERR_INVALID_ARG, "bad build mode");
   if (tuning->iht_early_exit > 1) return fail(BHT_ERR_INVALID_ARG, "iht_early_exit must be 0 or 1");
+  if (tuning->query_unroll > 2) return fail(BHT_ERR_INVALID_ARG, "query_unroll must be 0, 1 or 2");
   if (tuning->iht_early_exit && t->scheme != BHT_IHT)
     return fail(BHT_ERR_UNSUPPORTED, "early exit after the primary applies to iceberg tables");
   if (t->key_bits == 64) {
@@ -1029,6 +1033,7 @@ bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning) {
   t->grid_blocks = tuning->grid_blocks;
   t->build_mode = tuning->build_mode;
   t->iht_early_exit = tuning->iht_early_exit;
+  t->unroll = tuning->query_unroll == 2 ? 2 : 1;
   return BHT_OK;
 }
 
@@ -1039,6 +1044,7 @@ bht_status bht_get_tuning(const bht_table* t, bht_tuning* tuning) {
   tuning->grid_blocks = t->grid_blocks;
   tuning->build_mode = t->build_mode;
   tuning->iht_early_exit = t->iht_early_exit;
+  tuning->query_unroll = t->unroll == 2 ? 2 : 1;
   return BHT_OK;
 }
 
@@ -1159,8 +1165,9 @@ bht_status bht_batch_create(const bht_batch_entry* entries, uint32_t count, uint
     if (!seen.insert(t).second) return fail(BHT_ERR_INVALID_ARG, "table appears twice in batch");
     if (t->scheme != BHT_BCHT || t->key_bits != 32)
       return fail(BHT_ERR_UNSUPPORTED, "batches hold 32-bit bucketed cuckoo tables");
-    if (t->b != t0->b || t->tile != t0->tile)
-      return fail(BHT_ERR_INVALID_ARG, "tables of a batch share bucket size and tile width");
+    if (t->b != t0->b || t->tile != t0->tile || (t->unroll == 2) != (t0->unroll == 2))
+      return fail(BHT_ERR_INVALID_ARG,
+                  "tables of a batch share bucket size, tile width and query unroll");
     if (e.n_keys > t->slots) return fail(BHT_ERR_CAPACITY, "more pairs than slots");
     if ((e.n_keys && (!e.d_keys || !e.d_values)) ||
         (e.n_queries && (!e.d_queries || !e.d_out_values || !e.d_out_found)))
@@ -1168,10 +1175,11 @@ bht_status bht_batch_create(const bht_batch_entry* entries, uint32_t count, uint
   }
   const void* bk = nullptr;
   const void* fk = nullptr;
-#define BHT_BATCH_CASE(B_, W_)                                    \
-  if (t0->b == B_ && t0->tile == W_) {                            \
-    bk = (const void*)batch_build_kernel<B_, W_>;                 \
-    fk = (const void*)batch_find_kernel<B_, W_>;                  \
+#define BHT_BATCH_CASE(B_, W_)                                             \
+  if (t0->b == B_ && t0->tile == W_) {                                     \
+    bk = (const void*)batch_build_kernel<B_, W_>;                          \
+    fk = t0->unroll == 2 ? (const void*)batch_find_kernel<B_, W_, 2>       \
+                         : (const void*)batch_find_kernel<B_, W_, 1>;      \
   }
   BHT_BATCH_CASE(8, 4)
   BHT_BATCH_CASE(8, 8)

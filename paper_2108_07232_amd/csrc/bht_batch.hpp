@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void batch_build_kernel(const BatchTable* _
   }
 }
 
-template <int B, int W>
+template <int B, int W, int Q = 1>
 __global__ __launch_bounds__(kBlock) void batch_find_kernel(const BatchTable* __restrict__ tables,
                                                            const BatchItem* __restrict__ items,
                                                            uint64_t n_items,
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void batch_find_kernel(const BatchTable* __
     Range r;
     r.cursor = item.start;
     r.end = item.start + item.count;
-    cuckoo_find_chunk_range<B, W, false>(g, r);
+    cuckoo_find_chunk_range<B, W, false, Q>(g, r);
   }
 }
 

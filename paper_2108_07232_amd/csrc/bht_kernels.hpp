@@ -567,15 +567,9 @@ __device__ __forceinline__ void cuckoo_find_chunk_range(const FindArgs32& g, Ran
   }
 }
 
-// Queries per lane per chunk of the single-table query kernel (compile-time
-// tuning).
-#ifndef BHT_FIND_QPL
-#define BHT_FIND_QPL 1
-#endif
-
-template <int B, int W, bool COUNT>
+template <int B, int W, bool COUNT, int Q = 1>
 __global__ __launch_bounds__(kBlock) void cuckoo_find_chunk_kernel(FindArgs32 g) {
-  cuckoo_find_chunk_range<B, W, COUNT, BHT_FIND_QPL>(g, wave_range(g.n));
+  cuckoo_find_chunk_range<B, W, COUNT, Q>(g, wave_range(g.n));
 }
 
 // Parallel probing (the alternative noted in Section II-A): all h candidate

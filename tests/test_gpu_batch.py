@@ -12,7 +12,7 @@ from tests._util import dev, host_u32, host_u8
 pytestmark = pytest.mark.gpu
 
 
-def make_tables(count, lo, hi, seed, b=16, tile=8, lf=0.9):
+def make_tables(count, lo, hi, seed, b=16, tile=8, lf=0.9, unroll=0):
     import torch
     import paper_2108_07232_amd as bht
     sizes = datagen.log_uniform_sizes(count, lo, hi, seed)
@@ -22,7 +22,8 @@ def make_tables(count, lo, hi, seed, b=16, tile=8, lf=0.9):
         keys, vals = datagen.unique_keys(n, s), datagen.values(n, s)
         q = datagen.mixed_queries(n, n, 0.5, s)
         p = oracle.params_for("bcht", n, lf, s, b=b)
-        t = bht.Table(p.m * p.b, b, "bcht", p.a, p.c, rng_seed=p.rng_seed, tile=tile)
+        t = bht.Table(p.m * p.b, b, "bcht", p.a, p.c, rng_seed=p.rng_seed, tile=tile,
+                      query_unroll=unroll)
         tabs.append(dict(n=n, keys=keys, vals=vals, q=q, params=p, table=t,
                          dk=dev(keys), dv=dev(vals), dq=dev(q),
                          ov=torch.full((n,), 7, dtype=torch.int32, device="cuda"),
@@ -40,11 +41,12 @@ def check_outputs(tabs, statuses):
         np.testing.assert_array_equal(host_u32(d["ov"]), bv)
 
 
-@pytest.mark.parametrize("b,tile", [(16, 8), (8, 8), (32, 16), (16, 4)])
-def test_batch_matches_bruteforce_and_replays(b, tile):
+@pytest.mark.parametrize("b,tile,unroll", [(16, 8, 1), (8, 8, 1), (32, 16, 1), (16, 4, 1),
+                                           (16, 8, 2), (32, 16, 2)])
+def test_batch_matches_bruteforce_and_replays(b, tile, unroll):
     import torch
     import paper_2108_07232_amd as bht
-    tabs = make_tables(150, 6, 15, 3 + b, b=b, tile=tile)
+    tabs = make_tables(150, 6, 15, 3 + b, b=b, tile=tile, unroll=unroll)
     entries = [(d["table"].handle, d["dk"], d["dv"], d["dq"], d["ov"], d["of"]) for d in tabs]
     batch = bht.bht_batch_create(entries, item_size=1024)
     side = torch.cuda.Stream()
@@ -97,5 +99,17 @@ def test_batch_equals_plain_calls_and_reports_failures():
         np.testing.assert_array_equal(host_u32(v), batched[i][0])
         np.testing.assert_array_equal(host_u8(f), batched[i][1])
     bht.bht_batch_destroy(batch)
+    for d in tabs:
+        d["table"].close()
+
+
+def test_batch_rejects_mixed_query_unroll():
+    import paper_2108_07232_amd as bht
+    tabs = make_tables(4, 8, 10, 21)
+    bht.bht_set_tuning(tabs[2]["table"].handle, 8, 0, 0, 0, False, 2)
+    entries = [(d["table"].handle, d["dk"], d["dv"], d["dq"], d["ov"], d["of"]) for d in tabs]
+    with pytest.raises(bht.BhtError) as e:
+        bht.bht_batch_create(entries)
+    assert e.value.status == bht.BHT_ERR_INVALID_ARG
     for d in tabs:
         d["table"].close()

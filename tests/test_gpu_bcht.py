@@ -55,7 +55,7 @@ def build_with_retries(scheme, n, lf, b, seed0, h=None, tile=None, tries=8):
 
 # -------------------------------------------- find on oracle-built layouts
 
-@pytest.mark.parametrize("schedule", ["refill", "chunk", "parallel"])
+@pytest.mark.parametrize("schedule", ["refill", "chunk", "parallel", "chunk_unroll2"])
 @pytest.mark.parametrize("b,tile,n,lf", [
     (16, 8, 1 << 20, 0.9), (16, 4, 5000, 0.95), (16, 16, 4097, 0.9), (8, 8, 3001, 0.85),
     (8, 4, 777, 0.9), (32, 16, 6000, 0.95), (32, 8, 1000, 0.9), (4, 4, 2000, 0.8),
@@ -70,7 +70,11 @@ def test_find_on_oracle_layout(b, tile, n, lf, schedule):
         if st == oracle.OK:
             break
     assert st == oracle.OK
-    t = gpu_table(params, tile, schedule)
+    if schedule == "chunk_unroll2":
+        t = gpu_table(params, tile, "chunk")
+        bht().bht_set_tuning(t.handle, tile, "chunk", 0, 0, False, 2)
+    else:
+        t = gpu_table(params, tile, schedule)
     t.upload(layout, n)
     for frac in (1.0, 0.5, 0.0):
         q = datagen.mixed_queries(n, n, frac, 21)
