@@ -71,6 +71,12 @@ struct bht_batch {
   hipGraph_t graph;
   hipGraphExec_t exec;
   hipStream_t graph_stream;
+  // partitioned build of all tables (when every table fits one radix pass)
+  bool partitioned;
+  void* d_ws;                   // workspace: pairs, counters, descriptors
+  bht::BatchPartArgs pa;
+  const void* place_kernel;
+  const void* overflow_kernel;
 };
 
 struct bht_find_ctx {
@@ -1190,6 +1196,21 @@ bht_status bht_batch_create(const bht_batch_entry* entries, uint32_t count, uint
   BHT_BATCH_CASE(32, 16)
 #undef BHT_BATCH_CASE
   if (!bk) return fail(BHT_ERR_UNSUPPORTED, "no batched kernel for this bucket size and tile");
+  const void* pk = nullptr;
+  const void* ok = nullptr;
+#define BHT_BATCH_PCASE(B_, W_)                                   \
+  if (t0->b == B_ && t0->tile == W_) {                            \
+    pk = (const void*)batch_place_kernel<B_>;                     \
+    ok = (const void*)batch_overflow_kernel<B_, W_>;              \
+  }
+  BHT_BATCH_PCASE(8, 4)
+  BHT_BATCH_PCASE(8, 8)
+  BHT_BATCH_PCASE(16, 4)
+  BHT_BATCH_PCASE(16, 8)
+  BHT_BATCH_PCASE(16, 16)
+  BHT_BATCH_PCASE(32, 8)
+  BHT_BATCH_PCASE(32, 16)
+#undef BHT_BATCH_PCASE
 
   std::vector<BatchTable> tables(count);
   std::vector<BatchItem> fill, build, find;
@@ -1233,7 +1254,93 @@ bht_status bht_batch_create(const bht_batch_entry* entries, uint32_t count, uint
   std::vector<BatchItem> all(fill);
   all.insert(all.end(), build.begin(), build.end());
   all.insert(all.end(), find.begin(), find.end());
-  hipError_t e = hipMalloc(&b->d_tables, sizeof(BatchTable) * count);
+  hipError_t e = hipSuccess;
+  {
+    // Partitioned build: every table in one radix pass (at most kMaxFan bins
+    // of bin_slots / b buckets each), fewer than 2^32 pairs in all, and no
+    // table asks for the concurrent build.
+    const uint64_t R = bin_slots<16>() / t0->b;
+    uint64_t n_all = 0, bins = 0, counters = 0;
+    bool part = pk != nullptr;
+    for (uint32_t i = 0; i < count && part; ++i) {
+      const bht_table* t = entries[i].table;
+      const uint64_t nb = (t->m + R - 1) / R;
+      if (nb > kMaxFan || t->build_mode == BHT_BUILD_CONCURRENT) part = false;
+      n_all += entries[i].n_keys;
+      bins += nb;
+      counters += ((entries[i].n_keys + kPartChunkMax - 1) / kPartChunkMax) * nb;
+    }
+    if (n_all >= (1ull << 32) || bins >= (1ull << 32)) part = false;
+    if (part) {
+      std::vector<BatchPart> parts(count);
+      std::vector<BatchChunk> chunks;
+      std::vector<uint32_t> bin_table;
+      bin_table.reserve(bins);
+      uint64_t key_off = 0, hist_off = 0;
+      for (uint32_t i = 0; i < count; ++i) {
+        const bht_table* t = entries[i].table;
+        const uint64_t n = entries[i].n_keys;
+        const uint32_t nb = (uint32_t)((t->m + R - 1) / R);
+        parts[i] = {key_off, hist_off, (uint32_t)bin_table.size(), nb};
+        uint32_t local = 0;
+        for (uint64_t s0 = 0; s0 < n; s0 += kPartChunkMax, ++local)
+          chunks.push_back({i, local, s0, std::min<uint64_t>(kPartChunkMax, n - s0)});
+        for (uint32_t j = 0; j < nb; ++j) bin_table.push_back(i);
+        key_off += n;
+        hist_off += (uint64_t)local * nb;
+      }
+      // workspace carve-up (256-byte aligned pieces)
+      uint64_t off = 0;
+      auto take = [&off](uint64_t bytes) {
+        const uint64_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+      };
+      const uint64_t o_keys = take(n_all * 4), o_vals = take(n_all * 4);
+      const uint64_t o_hist = take(hist_off * 4);
+      const uint64_t o_total = take(bins * 8), o_cursor = take(bins * 8);
+      const uint64_t o_start = take(bins * 8), o_len = take(bins * 8);
+      const uint64_t o_ovf = take(bins * 4), o_bt = take(bins * 4);
+      const uint64_t o_parts = take(sizeof(BatchPart) * count);
+      const uint64_t o_chunks = take(sizeof(BatchChunk) * std::max<size_t>(1, chunks.size()));
+      const uint64_t o_head = take(16);
+      e = hipMalloc(&b->d_ws, off);
+      if (e == hipSuccess) {
+        char* w = static_cast<char*>(b->d_ws);
+        BatchPartArgs& pa = b->pa;
+        pa.parts = reinterpret_cast<const BatchPart*>(w + o_parts);
+        pa.chunks = reinterpret_cast<const BatchChunk*>(w + o_chunks);
+        pa.bin_table = reinterpret_cast<const uint32_t*>(w + o_bt);
+        pa.n_chunks = (uint32_t)chunks.size();
+        pa.count = count;
+        pa.nbins = (uint32_t)bins;
+        pa.bin_shift = log2_exact(R);
+        pa.hist = reinterpret_cast<uint32_t*>(w + o_hist);
+        pa.total = reinterpret_cast<unsigned long long*>(w + o_total);
+        pa.cursor = reinterpret_cast<unsigned long long*>(w + o_cursor);
+        pa.bin_start = reinterpret_cast<unsigned long long*>(w + o_start);
+        pa.bin_len = reinterpret_cast<unsigned long long*>(w + o_len);
+        pa.ovf_len = reinterpret_cast<uint32_t*>(w + o_ovf);
+        pa.keys = reinterpret_cast<uint32_t*>(w + o_keys);
+        pa.vals = reinterpret_cast<uint32_t*>(w + o_vals);
+        pa.head = reinterpret_cast<unsigned int*>(w + o_head);
+        e = hipMemcpy(w + o_parts, parts.data(), sizeof(BatchPart) * count, hipMemcpyHostToDevice);
+        if (e == hipSuccess && !chunks.empty())
+          e = hipMemcpy(w + o_chunks, chunks.data(), sizeof(BatchChunk) * chunks.size(),
+                        hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+          e = hipMemcpy(w + o_bt, bin_table.data(), 4 * bins, hipMemcpyHostToDevice);
+        b->partitioned = e == hipSuccess;
+        b->place_kernel = pk;
+        b->overflow_kernel = ok;
+      } else {
+        b->d_ws = nullptr;          // not enough memory: the concurrent build serves
+        e = hipSuccess;
+        (void)hipGetLastError();
+      }
+    }
+  }
+  if (e == hipSuccess) e = hipMalloc(&b->d_tables, sizeof(BatchTable) * count);
   if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(BatchItem) * std::max<size_t>(1, all.size()));
   if (e == hipSuccess) e = hipMalloc(&b->d_heads, 16);
   if (e == hipSuccess) e = hipMalloc(&b->d_status, sizeof(uint32_t) * count);
@@ -1246,6 +1353,8 @@ bht_status bht_batch_create(const bht_batch_entry* entries, uint32_t count, uint
     bht_batch_destroy(b);
     return fail(BHT_ERR_OOM, std::string("batch arrays: ") + hipGetErrorString(e));
   }
+  b->pa.tables = b->d_tables;
+  b->pa.status = b->d_status;
   *out = b;
   return BHT_OK;
 }
@@ -1255,12 +1364,25 @@ bht_status batch_launch(bht_batch* b, hipStream_t st) {
   batch_reset_kernel<<<std::max<uint32_t>(1, std::min<uint32_t>((b->count + 255) / 256, 1024)),
                        256, 0, st>>>(b->d_heads, b->d_status, b->count);
   HIP_TRY(hipGetLastError());
-  if (b->n_fill) {
+  if (b->partitioned) {
+    const BatchPartArgs& pa = b->pa;
+    batch_part_clear_kernel<<<std::max<uint32_t>(1, std::min<uint32_t>((pa.nbins + 255) / 256, 1024)),
+                              256, 0, st>>>(pa);
+    if (pa.n_chunks) batch_part_hist_kernel<<<pa.n_chunks, kPassBlock, 0, st>>>(pa);
+    batch_part_scan_kernel<<<pa.count, kPartBlock, 0, st>>>(pa);
+    if (pa.n_chunks) batch_part_scatter_kernel<<<pa.n_chunks, kPassBlock, 0, st>>>(pa);
+    reinterpret_cast<void (*)(BatchPartArgs)>(const_cast<void*>(b->place_kernel))
+        <<<pa.nbins, kBinBlock, 0, st>>>(pa);
+    const int og = grid_for(b->overflow_kernel, (uint64_t)pa.nbins * 64);
+    reinterpret_cast<void (*)(BatchPartArgs)>(const_cast<void*>(b->overflow_kernel))
+        <<<og, kBlock, 0, st>>>(pa);
+    HIP_TRY(hipGetLastError());
+  } else if (b->n_fill) {
     batch_fill_kernel<<<(int)std::min<uint64_t>(b->n_fill, 8192), kBlock, 0, st>>>(
         b->d_tables, b->d_items, b->n_fill);
     HIP_TRY(hipGetLastError());
   }
-  if (b->n_build) {
+  if (b->n_build && !b->partitioned) {
     const int grid = grid_for(b->build_kernel, b->n_build * kBlock);
     reinterpret_cast<void (*)(const BatchTable*, const BatchItem*, uint64_t, unsigned int*,
                               uint32_t*)>(const_cast<void*>(b->build_kernel))
@@ -1345,6 +1467,7 @@ void bht_batch_destroy(bht_batch* b) {
   if (b->d_heads) (void)hipFree(b->d_heads);
   if (b->d_status) (void)hipFree(b->d_status);
   if (b->h_status) (void)hipHostFree(b->h_status);
+  if (b->d_ws) (void)hipFree(b->d_ws);
   delete b;
 }
 

@@ -12,6 +12,7 @@
 // running on any XCD.
 #pragma once
 #include "bht_kernels.hpp"
+#include "bht_partition.hpp"
 
 namespace bht {
 
@@ -120,6 +121,145 @@ __global__ __launch_bounds__(kBlock) void batch_find_kernel(const BatchTable* __
     r.cursor = item.start;
     r.end = item.start + item.count;
     cuckoo_find_chunk_range<B, W, false, Q>(g, r);
+  }
+}
+
+// ---------------------------------------------- partitioned batched build
+//
+// The partitioned build of bht_partition.hpp for all tables of a batch at
+// once, with one radix pass per table: a table's pairs are grouped by the
+// bin (8,192 slots) of their first bucket within that table, so pairs of
+// different tables never mix and every table needs at most 1,024 bins.
+// Bins of all tables are numbered globally (table t owns bins
+// [bin_off_t, bin_off_t + nbins_t)); placement and overflow insertion run
+// over the global bins.  Work items of the counting and scatter kernels are
+// (table, chunk of at most 65,536 pairs); the partitioned pairs live in a
+// workspace where table t's pairs start at key_off_t.
+
+struct BatchPart {
+  unsigned long long key_off;    // first workspace position of the table's pairs
+  unsigned long long hist_off;   // first counter of the table's chunk histograms
+  uint32_t bin_off;              // first global bin of the table
+  uint32_t nbins;                // bins of the table (at most kMaxFan)
+};
+
+struct BatchChunk {
+  uint32_t table;
+  uint32_t local;                // chunk index within the table
+  unsigned long long start;      // first pair of the chunk, within the table's input
+  unsigned long long count;
+};
+
+struct BatchPartArgs {
+  const BatchTable* tables;
+  const BatchPart* parts;
+  const BatchChunk* chunks;
+  const uint32_t* bin_table;     // global bin -> table
+  uint32_t n_chunks;
+  uint32_t count;                // tables
+  uint32_t nbins;                // global bins
+  uint32_t bin_shift;            // bins of 2^bin_shift buckets
+  uint32_t* hist;
+  unsigned long long* total;     // per global bin
+  unsigned long long* cursor;
+  unsigned long long* bin_start;
+  unsigned long long* bin_len;
+  uint32_t* ovf_len;
+  uint32_t* keys;                // workspace
+  uint32_t* vals;
+  unsigned int* head;            // overflow queue
+  uint32_t* status;              // per table
+};
+
+__global__ void batch_part_clear_kernel(BatchPartArgs a) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint32_t j = i; j < a.nbins; j += gridDim.x * blockDim.x) a.total[j] = 0;
+  if (i == 0) *a.head = 0;
+}
+
+__global__ __launch_bounds__(kPassBlock) void batch_part_hist_kernel(BatchPartArgs a) {
+  const BatchChunk c = a.chunks[blockIdx.x];
+  const BatchTable& T = a.tables[c.table];
+  const BatchPart P = a.parts[c.table];
+  const Hash32 H = T.H;
+  const uint32_t shift = a.bin_shift;
+  const bool sentinel =
+      hist_range(T.keys, c.start, c.start + c.count, P.nbins,
+                 [&](uint32_t k) { return hash32(H, 0, k) >> shift; },
+                 a.hist + P.hist_off + (uint64_t)c.local * P.nbins, a.total + P.bin_off);
+  if (sentinel) atomicOr(a.status + c.table, kFlagSentinel);
+}
+
+// One block per table: the table's bin totals become workspace ranges.
+__global__ __launch_bounds__(kPartBlock) void batch_part_scan_kernel(BatchPartArgs a) {
+  __shared__ unsigned long long wt[kPartBlock / 64];
+  __shared__ unsigned long long base[kMaxFan];
+  const BatchPart P = a.parts[blockIdx.x];
+  const unsigned long long* tot = a.total + P.bin_off;
+  block_exclusive_scan<kPartBlock, unsigned long long>(tot, base, P.nbins, wt);
+  for (uint32_t d = threadIdx.x; d < P.nbins; d += kPartBlock) {
+    const uint64_t g = (uint64_t)P.bin_off + d;
+    a.cursor[g] = P.key_off + base[d];
+    a.bin_start[g] = P.key_off + base[d];
+    a.bin_len[g] = tot[d];
+  }
+}
+
+__global__ __launch_bounds__(kPassBlock) void batch_part_scatter_kernel(BatchPartArgs a) {
+  const BatchChunk c = a.chunks[blockIdx.x];
+  const BatchTable& T = a.tables[c.table];
+  const BatchPart P = a.parts[c.table];
+  const Hash32 H = T.H;
+  const uint32_t shift = a.bin_shift;
+  scatter_range(T.keys, T.vals, c.start, c.start + c.count, P.nbins,
+                [&](uint32_t k) { return hash32(H, 0, k) >> shift; },
+                a.hist + P.hist_off + (uint64_t)c.local * P.nbins, a.cursor + P.bin_off, a.keys,
+                a.vals);
+}
+
+// One block per global bin.
+template <int B>
+__global__ __launch_bounds__(kBinBlock) void batch_place_kernel(BatchPartArgs a) {
+  const uint32_t g = blockIdx.x;
+  const uint32_t t = a.bin_table[g];
+  const BatchTable& T = a.tables[t];
+  const uint32_t R = 1u << a.bin_shift;
+  const uint64_t first = (uint64_t)(g - a.parts[t].bin_off) * R;
+  const uint32_t nb = (uint64_t)T.H.m - first < (uint64_t)R ? (uint32_t)(T.H.m - first) : R;
+  const uint32_t ovf = place_bin<B>(T.slots, a.keys, a.vals, T.H, R, first, nb, a.bin_start[g],
+                                    a.bin_len[g], T.max_chain, T.rng_seed, g, a.status + t);
+  if (threadIdx.x == 0) a.ovf_len[g] = ovf;
+}
+
+// Pairs evicted during placement continue at their next bucket (cuckoo
+// insertion, Section III-A); waves take global bins from a queue.
+template <int B, int W>
+__global__ __launch_bounds__(kBlock) void batch_overflow_kernel(BatchPartArgs a) {
+  const uint32_t salt = lane_salt();
+  for (;;) {
+    const uint32_t g = part_queue_pop(a.head);
+    if (g >= a.nbins) break;
+    const uint32_t len = a.ovf_len[g];
+    if (len == 0) continue;
+    const uint32_t t = a.bin_table[g];
+    const BatchTable& T = a.tables[t];
+    BuildArgs32 b;
+    b.slots = T.slots;
+    b.keys = a.keys;
+    b.vals = a.vals;
+    b.n = 0;
+    b.status = a.status + t;
+    b.probe_total = nullptr;
+    b.H = T.H;
+    b.max_chain = T.max_chain;
+    b.rng_seed = T.rng_seed;
+    Range r;
+    r.cursor = a.bin_start[g];
+    r.end = r.cursor + len;
+    uint32_t probes = 0;
+    const uint32_t flags = cuckoo_build_range<B, W, false, true>(
+        b, r, T.rng_seed ^ salt ^ (g * 0x85EBCA6Bu), &probes);
+    if (flags) atomicOr(a.status + t, flags);
   }
 }
 

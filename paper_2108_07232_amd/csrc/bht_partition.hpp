@@ -188,14 +188,16 @@ __global__ void part_clear_kernel(PartMeta M, uint32_t fan1, uint32_t levels,
   if (i < 4) status[i] = 0;
 }
 
-// Digit counts of one chunk: stored per chunk (for the scatter's
-// reservations) and added to the range's digit totals.
-__global__ __launch_bounds__(kPassBlock) void part_hist_kernel(PartPass p) {
+// Digit counts of the pairs [begin, end) of in_k: stored in hrow (for the
+// scatter's reservations) and added to tot; returns whether the range held
+// the reserved empty key.  Every thread of the block calls it.
+template <typename DigitFn>
+__device__ __forceinline__ bool hist_range(const uint32_t* __restrict__ in_k, uint64_t begin,
+                                           uint64_t end, uint32_t fan, DigitFn digit,
+                                           uint32_t* __restrict__ hrow,
+                                           unsigned long long* __restrict__ tot) {
   __shared__ uint32_t cnt[kMaxFan];
-  uint32_t seg;
-  uint64_t begin, end;
-  if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
-  for (uint32_t d = threadIdx.x; d < p.fan; d += kPassBlock) cnt[d] = 0;
+  for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) cnt[d] = 0;
   __syncthreads();
   bool sentinel = false;
   constexpr int U = 8;
@@ -205,26 +207,39 @@ __global__ __launch_bounds__(kPassBlock) void part_hist_kernel(PartPass p) {
     for (int j = 0; j < U; ++j) {
       // branch-free loads: indices past the end re-read the last pair
       const uint64_t i = base + j * kPassBlock + threadIdx.x;
-      k[j] = p.in_k[i < end ? i : end - 1];
+      k[j] = in_k[i < end ? i : end - 1];
     }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const uint64_t i = base + j * kPassBlock + threadIdx.x;
       if (i < end) {
         sentinel |= k[j] == kEmptyKey;
-        atomicAdd(&cnt[part_digit(p.P, p.level, k[j])], 1u);
+        atomicAdd(&cnt[digit(k[j])], 1u);
       }
     }
   }
   __syncthreads();
-  uint32_t* h = p.level == 1 ? p.M.hist1 : p.M.hist2;
-  unsigned long long* tot = p.level == 1 ? p.M.total1 : p.M.total2 + (uint64_t)seg * kFan2;
-  for (uint32_t d = threadIdx.x; d < p.fan; d += kPassBlock) {
+  for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) {
     const uint32_t c = cnt[d];
-    h[(uint64_t)blockIdx.x * p.fan + d] = c;
+    hrow[d] = c;
     if (c) atomicAdd(&tot[d], (unsigned long long)c);
   }
-  if (p.level == 1 && sentinel) atomicOr(p.status, kFlagSentinel);
+  return sentinel;
+}
+
+// Digit counts of one chunk: stored per chunk (for the scatter's
+// reservations) and added to the range's digit totals.
+__global__ __launch_bounds__(kPassBlock) void part_hist_kernel(PartPass p) {
+  uint32_t seg;
+  uint64_t begin, end;
+  if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
+  uint32_t* h = (p.level == 1 ? p.M.hist1 : p.M.hist2) + (uint64_t)blockIdx.x * p.fan;
+  unsigned long long* tot = p.level == 1 ? p.M.total1 : p.M.total2 + (uint64_t)seg * kFan2;
+  const PartPlan& P = p.P;
+  const uint32_t level = p.level;
+  const bool sentinel = hist_range(p.in_k, begin, end, p.fan,
+                                   [&](uint32_t k) { return part_digit(P, level, k); }, h, tot);
+  if (level == 1 && sentinel) atomicOr(p.status, kFlagSentinel);
 }
 
 // First-pass totals -> output ranges.  One block.  With one pass the digits
@@ -271,24 +286,29 @@ __global__ __launch_bounds__(kPartBlock) void part_scan2_kernel(PartPlan P, Part
   }
 }
 
-// Writes one chunk in digit order: reserves the chunk's range of every digit,
-// then per sub-tile ranks pairs by digit in LDS and stores each digit's run
-// contiguously.  The next sub-tile's loads are issued before the current
-// one is ranked, so they overlap the on-chip work.
-__global__ __launch_bounds__(kPassBlock) void part_scatter_kernel(PartPass p) {
+// Writes the pairs [begin, end) in digit order: reserves the range of every
+// digit (hrow holds the range's digit counts, cur the digits' next output
+// positions), then per sub-tile ranks pairs by digit in LDS and stores each
+// digit's run contiguously.  The next sub-tile's loads are issued before the
+// current one is ranked, so they overlap the on-chip work.  Positions are
+// below 2^32 (the partitioned path takes fewer than 2^32 pairs).  Every
+// thread of the block calls it.
+template <typename DigitFn>
+__device__ __forceinline__ void scatter_range(const uint32_t* __restrict__ in_k,
+                                              const uint32_t* __restrict__ in_v, uint64_t begin,
+                                              uint64_t end, uint32_t fan, DigitFn digit,
+                                              const uint32_t* __restrict__ hrow,
+                                              unsigned long long* __restrict__ cur,
+                                              uint32_t* __restrict__ out_k,
+                                              uint32_t* __restrict__ out_v) {
   __shared__ uint32_t sk[kPartSub];
   __shared__ uint32_t sv[kPartSub];
   __shared__ uint32_t cnt[kMaxFan];
   __shared__ uint32_t start[kMaxFan];
-  __shared__ uint32_t run[kMaxFan];        // positions < 2^32 (n < 2^32 on this path)
+  __shared__ uint32_t run[kMaxFan];
   __shared__ uint32_t wt[kPassBlock / 64];
-  uint32_t seg;
-  uint64_t begin, end;
-  if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
-  const uint32_t* h = (p.level == 1 ? p.M.hist1 : p.M.hist2) + (uint64_t)blockIdx.x * p.fan;
-  unsigned long long* cur = p.level == 1 ? p.M.cursor1 : p.M.cursor2 + (uint64_t)seg * kFan2;
-  for (uint32_t d = threadIdx.x; d < p.fan; d += kPassBlock) {
-    const uint32_t c = h[d];
+  for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) {
+    const uint32_t c = hrow[d];
     run[d] = c ? (uint32_t)atomicAdd(&cur[d], (unsigned long long)c) : 0u;
   }
   // Loads are branch-free (indices past the end re-read the last pair, and
@@ -299,35 +319,37 @@ __global__ __launch_bounds__(kPassBlock) void part_scatter_kernel(PartPass p) {
 #pragma unroll
   for (int j = 0; j < kPartPer; ++j) {
     const uint64_t i = begin + j * kPassBlock + threadIdx.x;
-    k[j] = p.in_k[i < end ? i : last];
-    v[j] = p.in_v[i < end ? i : last];
+    k[j] = in_k[i < end ? i : last];
+    v[j] = in_v[i < end ? i : last];
   }
   for (uint64_t sub = begin; sub < end; sub += kPartSub) {
     uint32_t nk[kPartPer], nv[kPartPer];
 #pragma unroll
     for (int j = 0; j < kPartPer; ++j) {
       const uint64_t i = sub + kPartSub + j * kPassBlock + threadIdx.x;
-      nk[j] = p.in_k[i < end ? i : last];
-      nv[j] = p.in_v[i < end ? i : last];
+      nk[j] = in_k[i < end ? i : last];
+      nv[j] = in_v[i < end ? i : last];
     }
-    for (uint32_t d = threadIdx.x; d < p.fan; d += kPassBlock) cnt[d] = 0;
+    for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) cnt[d] = 0;
     __syncthreads();
-    uint32_t rank[kPartPer], dig[kPartPer];
+    // rank within the digit (< 2^14) and digit (< 2^10) share a register
+    static_assert(kPartSub <= (1 << 22) && kMaxFan <= 1024, "rank and digit packing");
+    uint32_t rd[kPartPer];
 #pragma unroll
     for (int j = 0; j < kPartPer; ++j) {
       const uint64_t i = sub + j * kPassBlock + threadIdx.x;
       if (i < end) {
-        dig[j] = part_digit(p.P, p.level, k[j]);
-        rank[j] = atomicAdd(&cnt[dig[j]], 1u);
+        const uint32_t d = digit(k[j]);
+        rd[j] = (atomicAdd(&cnt[d], 1u) << 10) | d;
       }
     }
     __syncthreads();
-    block_exclusive_scan<kPassBlock, uint32_t>(cnt, start, p.fan, wt);
+    block_exclusive_scan<kPassBlock, uint32_t>(cnt, start, fan, wt);
 #pragma unroll
     for (int j = 0; j < kPartPer; ++j) {
       const uint64_t i = sub + j * kPassBlock + threadIdx.x;
       if (i < end) {
-        const uint32_t pos = start[dig[j]] + rank[j];
+        const uint32_t pos = start[rd[j] & 1023u] + (rd[j] >> 10);
         sk[pos] = k[j];
         sv[pos] = v[j];
       }
@@ -341,14 +363,14 @@ __global__ __launch_bounds__(kPassBlock) void part_scatter_kernel(PartPass p) {
       const uint32_t i = j * kPassBlock + threadIdx.x;
       if (i < count) {
         const uint32_t key = sk[i];
-        const uint32_t d = part_digit(p.P, p.level, key);     // recomputed, not stored
+        const uint32_t d = digit(key);                        // recomputed, not stored
         const uint32_t dst = run[d] + (i - start[d]);
-        p.out_k[dst] = key;
-        p.out_v[dst] = sv[i];
+        out_k[dst] = key;
+        out_v[dst] = sv[i];
       }
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < p.fan; d += kPassBlock) run[d] += cnt[d];
+    for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) run[d] += cnt[d];
     // the next sub-tile's first barrier orders these updates before use
 #pragma unroll
     for (int j = 0; j < kPartPer; ++j) {
@@ -356,6 +378,18 @@ __global__ __launch_bounds__(kPassBlock) void part_scatter_kernel(PartPass p) {
       v[j] = nv[j];
     }
   }
+}
+
+__global__ __launch_bounds__(kPassBlock) void part_scatter_kernel(PartPass p) {
+  uint32_t seg;
+  uint64_t begin, end;
+  if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
+  const uint32_t* h = (p.level == 1 ? p.M.hist1 : p.M.hist2) + (uint64_t)blockIdx.x * p.fan;
+  unsigned long long* cur = p.level == 1 ? p.M.cursor1 : p.M.cursor2 + (uint64_t)seg * kFan2;
+  const PartPlan& P = p.P;
+  const uint32_t level = p.level;
+  scatter_range(p.in_k, p.in_v, begin, end, p.fan,
+                [&](uint32_t k) { return part_digit(P, level, k); }, h, cur, p.out_k, p.out_v);
 }
 
 struct BinArgs {
@@ -375,36 +409,40 @@ struct BinArgs {
 // claimed slot is then written) it exchanges itself with a random slot of
 // the bucket, and the evicted pair is written to the front of the bin's
 // input range, to continue at its next bucket in the overflow kernel.  The
-// bin's buckets, empty slots included, are then stored whole.
+// bin's buckets, empty slots included, are then stored whole.  The bin is
+// buckets [first, first + nb) of the table (nb <= R <= slots / B); its pairs
+// are keys/vals[s0, s0 + len).  Returns (in every thread) the number of
+// evicted pairs; raises flags in *status.  Every thread of the block calls it.
 template <int B>
-__global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
+__device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
+                                              uint32_t* __restrict__ keys,
+                                              uint32_t* __restrict__ vals, const Hash32& H,
+                                              uint32_t R, uint64_t first, uint32_t nb,
+                                              uint64_t s0, uint64_t len, uint32_t max_chain,
+                                              uint32_t rng_seed, uint32_t salt,
+                                              uint32_t* __restrict__ status) {
   constexpr int S = bin_slots<B>();
   constexpr int RMAX = S / B;                    // buckets per bin, at most
   __shared__ u64x2 tbl2[S / 2];
   __shared__ uint32_t load[RMAX];
   __shared__ uint32_t ovf;
   unsigned long long* tbl = reinterpret_cast<unsigned long long*>(tbl2);
-  const uint32_t R = 1u << a.P.bin_shift;        // buckets per bin of this plan (<= RMAX)
-  const uint32_t bin = blockIdx.x;
-  const uint64_t first = (uint64_t)bin * R;
-  const uint32_t nb = (uint64_t)a.P.H.m - first < (uint64_t)R ? (uint32_t)(a.P.H.m - first) : R;
   const u64x2 e2 = {kEmptyPair, kEmptyPair};
   for (uint32_t i = threadIdx.x; i < (R * B + 1) / 2; i += kBinBlock) tbl2[i] = e2;
   for (uint32_t i = threadIdx.x; i < R; i += kBinBlock) load[i] = 0;
   if (threadIdx.x == 0) ovf = 0;
-  uint32_t rng = a.rng_seed ^ (bin * 0x9E3779B9u) ^ (threadIdx.x * 0x85EBCA6Bu);
+  uint32_t rng = rng_seed ^ (salt * 0x9E3779B9u) ^ (threadIdx.x * 0x85EBCA6Bu);
   if (rng == 0) rng = 0x2545F491u;
   uint32_t flags = 0;
   __syncthreads();
-  const uint64_t s0 = a.M.bin_start[bin], len = a.M.bin_len[bin];
   for (uint64_t r0 = 0; r0 < len; r0 += (uint64_t)kBinBlock * kBinPer) {
     uint32_t k[kBinPer], v[kBinPer], full[kBinPer];
 #pragma unroll
     for (int j = 0; j < kBinPer; ++j) {
       // branch-free loads: indices past the end re-read the bin's last pair
       const uint64_t i = r0 + j * kBinBlock + threadIdx.x;
-      k[j] = a.keys[s0 + (i < len ? i : len - 1)];
-      v[j] = a.vals[s0 + (i < len ? i : len - 1)];
+      k[j] = keys[s0 + (i < len ? i : len - 1)];
+      v[j] = vals[s0 + (i < len ? i : len - 1)];
     }
 #pragma unroll
     for (int j = 0; j < kBinPer; ++j) {
@@ -412,7 +450,7 @@ __global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
       const uint64_t i = r0 + j * kBinBlock + threadIdx.x;
       if (i < len) {
         // lb < nb by construction of the partition
-        const uint32_t lb = hash32(a.P.H, 0, k[j]) - (uint32_t)first;
+        const uint32_t lb = hash32(H, 0, k[j]) - (uint32_t)first;
         if (lb >= nb) {
           flags |= kFlagFailed;
         } else {
@@ -430,7 +468,7 @@ __global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
 #pragma unroll
     for (int j = 0; j < kBinPer; ++j) {
       if (full[j] != ~0u) {
-        if (a.max_chain == 0) {
+        if (max_chain == 0) {
           flags |= kFlagFailed;
           full[j] = ~0u;
         } else {
@@ -446,21 +484,33 @@ __global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
 #pragma unroll
     for (int j = 0; j < kBinPer; ++j) {
       if (full[j] != ~0u) {
-        a.keys[s0 + full[j]] = k[j];
-        a.vals[s0 + full[j]] = v[j];
+        keys[s0 + full[j]] = k[j];
+        vals[s0 + full[j]] = v[j];
       }
     }
   }
   __syncthreads();
   const uint64_t words = (uint64_t)nb * B;
-  u64x2* dst2 = reinterpret_cast<u64x2*>(a.slots + first * B);
+  u64x2* dst2 = reinterpret_cast<u64x2*>(slots + first * B);
   for (uint32_t i = threadIdx.x; i < words / 2; i += kBinBlock) dst2[i] = tbl2[i];
-  if ((words & 1) && threadIdx.x == 0) a.slots[first * B + words - 1] = tbl[words - 1];
+  if ((words & 1) && threadIdx.x == 0) slots[first * B + words - 1] = tbl[words - 1];
+  if (flags) atomicOr(status, flags);
+  return ovf;
+}
+
+template <int B>
+__global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
+  const uint32_t R = 1u << a.P.bin_shift;        // buckets per bin of this plan
+  const uint32_t bin = blockIdx.x;
+  const uint64_t first = (uint64_t)bin * R;
+  const uint32_t nb = (uint64_t)a.P.H.m - first < (uint64_t)R ? (uint32_t)(a.P.H.m - first) : R;
+  const uint32_t ovf =
+      place_bin<B>(a.slots, a.keys, a.vals, a.P.H, R, first, nb, a.M.bin_start[bin],
+                   a.M.bin_len[bin], a.max_chain, a.rng_seed, bin, a.status);
   if (threadIdx.x == 0) {
     a.M.ovf_len[bin] = ovf;
     if (ovf) atomicAdd(a.status + 1, ovf);       // evicted pairs of the build
   }
-  if (flags) atomicOr(a.status, flags);
 }
 
 struct OverflowArgs {
