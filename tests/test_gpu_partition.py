@@ -229,7 +229,7 @@ def test_build_with_caller_workspace():
     assert B.bht_build_stats(t.handle)[0]
     check_table(t, params, keys, vals)
     t.close()
-    p2 = oracle.params_for("bp2ht", n, 0.8, 1101)
+    p2 = oracle.params_for("bp2ht", n, 0.6, 1101)        # well below the scheme's limit
     t = B.Table(p2.m * 16, 16, "bp2ht", p2.a, p2.c)
     assert B.bht_build_workspace_bytes(t.handle, n) == 0
     B.bht_build_async_in(t.handle, dk, dv, ws)
