@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kPartBlock) void batch_part_scan_kernel(BatchPartAr
   }
 }
 
-__global__ __launch_bounds__(kPassBlock) void batch_part_scatter_kernel(BatchPartArgs a) {
+__global__ __launch_bounds__(kPassBlock, kScatterBlocksPerCU) void batch_part_scatter_kernel(BatchPartArgs a) {
   const BatchChunk c = a.chunks[blockIdx.x];
   const BatchTable& T = a.tables[c.table];
   const BatchPart P = a.parts[c.table];

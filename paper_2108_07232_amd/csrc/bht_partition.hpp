@@ -45,6 +45,10 @@ namespace bht {
 #ifndef BHT_PASS_PER
 #define BHT_PASS_PER 16
 #endif
+#ifndef BHT_SCATTER_BLOCKS_PER_CU
+#define BHT_SCATTER_BLOCKS_PER_CU 1
+#endif
+constexpr int kScatterBlocksPerCU = BHT_SCATTER_BLOCKS_PER_CU;   // occupancy the scatter is compiled for
 constexpr int kPartBlock = 256;                        // threads per scan block
 constexpr int kPassBlock = BHT_PASS_BLOCK;
 constexpr int kPartSub = BHT_PASS_PER * kPassBlock;
@@ -380,7 +384,7 @@ __device__ __forceinline__ void scatter_range(const uint32_t* __restrict__ in_k,
   }
 }
 
-__global__ __launch_bounds__(kPassBlock) void part_scatter_kernel(PartPass p) {
+__global__ __launch_bounds__(kPassBlock, kScatterBlocksPerCU) void part_scatter_kernel(PartPass p) {
   uint32_t seg;
   uint64_t begin, end;
   if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
