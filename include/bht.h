@@ -163,7 +163,7 @@ bht_status bht_build_retry(bht_table* t, const void* d_keys, const void* d_value
                            uint64_t seed, uint32_t max_attempts, uint32_t* attempts_out,
                            void* stream);
 
-/* Statistics of the last successful 32-bit build: *partitioned = 1 if it
+/* Statistics of the last successful build: *partitioned = 1 if it
  * took the partitioned path (see bht_tuning), else 0.  For a partitioned
  * build, *evicted = pairs that met a full first bucket and evicted a
  * resident on chip, and *overflow_probes = bucket reads made while those
@@ -199,7 +199,14 @@ bht_status bht_build_async_in(bht_table* t, const uint32_t* d_keys, const uint32
 bht_status bht_find(const bht_table* t, const uint32_t* d_queries, uint64_t n,
                     uint32_t* d_out_values, uint8_t* d_out_found, void* stream);
 
-/* 64-bit keys and values (bucketed cuckoo, 16-byte slots). */
+/* 64-bit keys and values (bucketed cuckoo, 16-byte slots, 8 per bucket;
+ * not in the paper, whose pairs fit one 64-bit word).  Keys 2^64 - 1 and
+ * 2^64 - 2 are reserved (SENTINEL_KEY).  bht_build64 is synchronous like
+ * bht_build and follows the table's build_mode: the partitioned path takes
+ * builds of at least 2^18 pairs under BHT_BUILD_AUTO (workspace of about
+ * 16 bytes per pair), and its on-chip step exchanges 16-byte pairs in
+ * rounds ranked by each bucket's load counter, again the serial algorithm
+ * of Section III-A in one insertion order. */
 bht_status bht_build64(bht_table* t, const uint64_t* d_keys, const uint64_t* d_values,
                        uint64_t n, void* stream);
 bht_status bht_find64(const bht_table* t, const uint64_t* d_queries, uint64_t n,
@@ -224,7 +231,8 @@ bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint6
  * candidate buckets of a query are read at once, Section II-A's parallel
  * query: one memory latency per query instead of up to h, at h probes per
  * query; results are identical).  grid_blocks: blocks of 256 threads per launch,
- * 0 = as many as the device keeps resident.  build_mode (BCHT and CHT1):
+ * 0 = as many as the device keeps resident.  build_mode (BCHT, CHT1 and
+ * the 64-bit table; 64-bit tables take tile_width 8 and ignore the rest):
  * BHT_BUILD_CONCURRENT inserts every pair with the concurrent cuckoo
  * kernel (Section V-B); BHT_BUILD_PARTITIONED first groups the pairs by the
  * region of their first bucket (two streaming radix passes), places each

@@ -18,6 +18,7 @@
 #include "bht_wide.hpp"
 #include "bht_batch.hpp"
 #include "bht_partition.hpp"
+#include "bht_wide_partition.hpp"
 
 using namespace bht;
 
@@ -396,13 +397,15 @@ uint32_t log2_exact(uint64_t x) {
 // so small tables get enough bins to fill the device; chunks shrink for the
 // same reason.
 bool part_plan(const bht_table* t, uint64_t n, PartPlan* P) {
-  const uint64_t S = t->b == 1 ? bin_slots<1>() : bin_slots<16>();
+  const uint64_t S = t->key_bits == 64 ? kBin64Slots : t->b == 1 ? bin_slots<1>() : bin_slots<16>();
   uint64_t R = S / t->b;
   while (R > 32 && (t->m + R / 2 - 1) / (R / 2) <= kMaxFan) R /= 2;
   const uint64_t nbins = (t->m + R - 1) / R;
   const uint64_t per = (n + (uint64_t)kPartSub * 512 - 1) / ((uint64_t)kPartSub * 512);
+  *P = PartPlan{};
   P->chunk = kPartSub * (uint32_t)std::min<uint64_t>(std::max<uint64_t>(per, 1), kPartChunkMax / kPartSub);
-  P->H = make_hash32(t->params, t->m, t->params.num_hashes);
+  if (t->key_bits == 64) P->H64 = make_hash64(t->params, t->m, t->params.num_hashes);
+  else P->H = make_hash32(t->params, t->m, t->params.num_hashes);
   P->bin_shift = log2_exact(R);
   P->nbins = (uint32_t)nbins;
   if (nbins <= kMaxFan) {
@@ -424,7 +427,7 @@ struct PartLayout {
   uint64_t chunks1, chunks2;
 };
 
-PartLayout part_layout(const PartPlan& P, uint64_t n) {
+PartLayout part_layout(const PartPlan& P, uint64_t n, uint32_t word_bytes = 4) {
   PartLayout L{};
   uint64_t off = 0;
   auto take = [&off](uint64_t bytes) {
@@ -447,8 +450,8 @@ PartLayout part_layout(const PartPlan& P, uint64_t n) {
   L.bin_len = take(P.nbins * 8ull);
   L.ovf_len = take(P.nbins * 4ull);
   L.head = take(4);
-  L.keys = take(n * 4);
-  L.vals = take(n * 4);
+  L.keys = take(n * word_bytes);
+  L.vals = take(n * word_bytes);
   L.bytes = off;
   return L;
 }
@@ -456,6 +459,7 @@ PartLayout part_layout(const PartPlan& P, uint64_t n) {
 bool use_partitioned(const bht_table* t, uint64_t n, bool counting) {
   if (counting || n == 0 || n >= (1ull << 32)) return false;
   if (t->scheme != BHT_BCHT && t->scheme != BHT_CHT1) return false;
+  if (t->key_bits == 64 && t->b != 8) return false;
   if (t->build_mode == BHT_BUILD_CONCURRENT) return false;
   PartPlan P;
   if (!part_plan(t, n, &P)) return false;
@@ -463,17 +467,10 @@ bool use_partitioned(const bht_table* t, uint64_t n, bool counting) {
   return n >= kPartMinKeys && t->owns_memory;
 }
 
-// ws: caller-owned workspace of ws_bytes, or null for the table's own
-// (allocated on first use and grown as needed).
-bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_t* vals,
-                               uint64_t n, hipStream_t st, void* ws = nullptr,
-                               uint64_t ws_bytes = 0) {
-  PartPlan P;
-  if (!part_plan(t, n, &P)) return fail(BHT_ERR_UNSUPPORTED, "table too large to partition");
-  PartKernels K;
-  if (!part_kernels(t->b, t->tile, &K))
-    return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
-  const PartLayout L = part_layout(P, n);
+// *w <- the workspace for layout L: the caller's ws (of ws_bytes), or, when
+// ws is null, the table's own, allocated on first use and grown as needed.
+bht_status part_workspace(bht_table* t, const PartLayout& L, hipStream_t st, void* ws,
+                          uint64_t ws_bytes, char** w) {
   if (ws && (ws_bytes < L.bytes || (reinterpret_cast<uintptr_t>(ws) & 255)))
     return fail(BHT_ERR_INVALID_ARG, "workspace too small or not 256-byte aligned");
   if (!ws && t->part_bytes < L.bytes) {
@@ -491,7 +488,11 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
     }
     t->part_bytes = L.bytes;
   }
-  char* w = static_cast<char*>(ws ? ws : t->d_part);
+  *w = static_cast<char*>(ws ? ws : t->d_part);
+  return BHT_OK;
+}
+
+PartMeta part_meta(const PartLayout& L, char* w) {
   PartMeta M;
   M.hist1 = reinterpret_cast<uint32_t*>(w + L.hist1);
   M.hist2 = reinterpret_cast<uint32_t*>(w + L.hist2);
@@ -506,6 +507,101 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
   M.bin_len = reinterpret_cast<unsigned long long*>(w + L.bin_len);
   M.ovf_len = reinterpret_cast<uint32_t*>(w + L.ovf_len);
   M.head = reinterpret_cast<unsigned int*>(w + L.head);
+  return M;
+}
+
+// Partitioned build of a 64-bit table (8-slot buckets); library-owned
+// workspace.
+bht_status build64_partitioned(bht_table* t, const uint64_t* keys, const uint64_t* vals,
+                               uint64_t n, hipStream_t st) {
+  PartPlan P;
+  if (!part_plan(t, n, &P)) return fail(BHT_ERR_UNSUPPORTED, "table too large to partition");
+  const PartLayout L = part_layout(P, n, 8);
+  char* w = nullptr;
+  bht_status ws_status = part_workspace(t, L, st, nullptr, 0, &w);
+  if (ws_status != BHT_OK) return ws_status;
+  const PartMeta M = part_meta(L, w);
+  uint64_t* keys2 = reinterpret_cast<uint64_t*>(w + L.keys);
+  uint64_t* vals2 = reinterpret_cast<uint64_t*>(w + L.vals);
+  // the first of two passes writes into the slot array (2 words per slot)
+  uint64_t* mid_k = t->d_slots;
+  uint64_t* mid_v = mid_k + n;
+
+  if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
+  part_clear_kernel<<<64, kPartBlock, 0, st>>>(M, P.fan1, P.levels, t->d_status);
+  PartPass64 p1;
+  p1.in_k = keys;
+  p1.in_v = vals;
+  p1.out_k = P.levels == 1 ? keys2 : mid_k;
+  p1.out_v = P.levels == 1 ? vals2 : mid_v;
+  p1.n = n;
+  p1.level = 1;
+  p1.fan = P.fan1;
+  p1.status = t->d_status;
+  p1.P = P;
+  p1.M = M;
+  part_hist64_kernel<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
+  part_scan1_kernel<<<1, kPartBlock, 0, st>>>(P, M);
+  part_scatter64_kernel<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
+  if (P.levels == 2) {
+    PartPass64 p2 = p1;
+    p2.in_k = mid_k;
+    p2.in_v = mid_v;
+    p2.out_k = keys2;
+    p2.out_v = vals2;
+    p2.level = 2;
+    p2.fan = kFan2;
+    part_hist64_kernel<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
+    part_scan2_kernel<<<P.fan1, kPartBlock, 0, st>>>(P, M);
+    part_scatter64_kernel<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
+  }
+  BinArgs64 ba;
+  ba.slots = t->d_slots;
+  ba.keys = keys2;
+  ba.vals = vals2;
+  ba.status = t->d_status;
+  ba.max_chain = t->params.max_chain;
+  ba.rng_seed = (uint32_t)t->params.rng_seed;
+  ba.P = P;
+  ba.M = M;
+  bin_place64_kernel<<<P.nbins, kBinBlock, 0, st>>>(ba);
+  WideOverflowArgs oa;
+  oa.g.slots = t->d_slots;
+  oa.g.keys = keys2;
+  oa.g.vals = vals2;
+  oa.g.n = n;
+  oa.g.status = t->d_status;
+  oa.g.H = P.H64;
+  oa.g.max_chain = t->params.max_chain;
+  oa.g.rng_seed = (uint32_t)t->params.rng_seed;
+  oa.M = M;
+  oa.nbins = P.nbins;
+  const int og = grid_for((const void*)wide_overflow_kernel<8>, (uint64_t)P.nbins * 64,
+                          t->grid_blocks);
+  wide_overflow_kernel<8><<<og, kBlock, 0, st>>>(oa);
+  HIP_TRY(hipGetLastError());
+  if (t->timing) HIP_TRY(hipEventRecord(t->ev[1], st));
+  t->build_timed = t->timing;
+  t->pending = true;
+  t->pending_n = n;
+  t->pending_partitioned = true;
+  return BHT_OK;
+}
+
+// ws: caller-owned workspace of ws_bytes, or null for the table's own.
+bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_t* vals,
+                               uint64_t n, hipStream_t st, void* ws = nullptr,
+                               uint64_t ws_bytes = 0) {
+  PartPlan P;
+  if (!part_plan(t, n, &P)) return fail(BHT_ERR_UNSUPPORTED, "table too large to partition");
+  PartKernels K;
+  if (!part_kernels(t->b, t->tile, &K))
+    return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
+  const PartLayout L = part_layout(P, n);
+  char* w = nullptr;
+  bht_status ws_status = part_workspace(t, L, st, ws, ws_bytes, &w);
+  if (ws_status != BHT_OK) return ws_status;
+  const PartMeta M = part_meta(L, w);
   uint32_t* keys2 = reinterpret_cast<uint32_t*>(w + L.keys);
   uint32_t* vals2 = reinterpret_cast<uint32_t*>(w + L.vals);
   // With two passes the first pass writes into the table's slot array,
@@ -526,9 +622,9 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
   p1.status = t->d_status;
   p1.P = P;
   p1.M = M;
-  part_hist_kernel<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
+  part_hist_kernel<uint32_t><<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
   part_scan1_kernel<<<1, kPartBlock, 0, st>>>(P, M);
-  part_scatter_kernel<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
+  part_scatter_kernel<uint32_t><<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
   if (P.levels == 2) {
     PartPass p2 = p1;
     p2.in_k = mid_k;
@@ -537,9 +633,9 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
     p2.out_v = vals2;
     p2.level = 2;
     p2.fan = kFan2;
-    part_hist_kernel<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
+    part_hist_kernel<uint32_t><<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
     part_scan2_kernel<<<P.fan1, kPartBlock, 0, st>>>(P, M);
-    part_scatter_kernel<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
+    part_scatter_kernel<uint32_t><<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
   }
   BinArgs ba;
   ba.slots = t->d_slots;
@@ -864,7 +960,9 @@ bht_status bht_build_wait(bht_table* t, void* stream) {
   HIP_TRY(hipStreamSynchronize(st));
   t->pending = false;
   const uint32_t flags = t->h_status[0];
-  if (flags & kFlagSentinel) return fail(BHT_ERR_SENTINEL_KEY, "input holds key 0xFFFFFFFF");
+  if (flags & kFlagSentinel)
+    return fail(BHT_ERR_SENTINEL_KEY, t->key_bits == 64 ? "input holds a reserved 64-bit key"
+                                                        : "input holds key 0xFFFFFFFF");
   if (flags & kFlagFailed) return fail(BHT_ERR_BUILD_FAILED, "eviction cap reached");
   t->built = true;
   t->n_stored = t->pending_n;
@@ -967,6 +1065,12 @@ bht_status bht_build64(bht_table* t, const uint64_t* d_keys, const uint64_t* d_v
   if (t->b != 8) return fail(BHT_ERR_UNSUPPORTED, "64-bit tables use 8-slot buckets");
   hipStream_t st = as_stream(stream);
   t->built = false;
+  t->pending_partitioned = false;
+  if (use_partitioned(t, n, false)) {
+    bht_status s = build64_partitioned(t, d_keys, d_values, n, st);
+    if (s != BHT_OK) return s;
+    return bht_build_wait(t, stream);
+  }
   bht_status s = launch_fill(t, st);
   if (s != BHT_OK) return s;
   if (n) {
@@ -1029,6 +1133,7 @@ bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning) {
   if (t->key_bits == 64) {
     if (w != 8) return fail(BHT_ERR_UNSUPPORTED, "64-bit tables read buckets with 8 lanes");
     t->grid_blocks = tuning->grid_blocks;
+    t->build_mode = tuning->build_mode;
     return BHT_OK;
   }
   KernelSet ks;

@@ -65,7 +65,8 @@ template <int B>
 constexpr int bin_slots() { return B == 1 ? 4096 : 8192; }
 
 struct PartPlan {
-  Hash32 H;             // first hash (index 0) and bucket count
+  Hash32 H;             // first hash (index 0) and bucket count, 32-bit keys
+  Hash64 H64;           // the same for 64-bit keys
   uint32_t bin_shift;   // bin = H_0(k) >> bin_shift: 2^bin_shift buckets per bin
   uint32_t levels;      // radix passes: 1 or 2
   uint32_t fan1;        // digits of the first pass
@@ -90,13 +91,15 @@ struct PartMeta {
   unsigned int* head;            // overflow queue head
 };
 
-// One radix pass.  Level 1 reads the caller's arrays as a single range of n
-// pairs; level 2 reads the first pass's output as fan1 ranges (seg_*).
-struct PartPass {
-  const uint32_t* in_k;
-  const uint32_t* in_v;
-  uint32_t* out_k;
-  uint32_t* out_v;
+// One radix pass over pairs of T keys and T values.  Level 1 reads the
+// caller's arrays as a single range of n pairs; level 2 reads the first
+// pass's output as fan1 ranges (seg_*).
+template <typename T>
+struct PartPassT {
+  const T* in_k;
+  const T* in_v;
+  T* out_k;
+  T* out_v;
   uint64_t n;
   uint32_t level;
   uint32_t fan;
@@ -104,16 +107,26 @@ struct PartPass {
   PartPlan P;
   PartMeta M;
 };
+using PartPass = PartPassT<uint32_t>;
+using PartPass64 = PartPassT<uint64_t>;
 
-__device__ __forceinline__ uint32_t part_digit(const PartPlan& P, uint32_t level, uint32_t key) {
-  const uint32_t bin = hash32(P.H, 0, key) >> P.bin_shift;
+__device__ __forceinline__ uint32_t part_split(const PartPlan& P, uint32_t level, uint32_t bin) {
   if (P.levels == 1) return bin;
   return level == 1 ? bin >> 8 : bin & (kFan2 - 1);
 }
 
+__device__ __forceinline__ uint32_t part_digit(const PartPlan& P, uint32_t level, uint32_t key) {
+  return part_split(P, level, hash32(P.H, 0, key) >> P.bin_shift);
+}
+
+__device__ __forceinline__ uint32_t part_digit(const PartPlan& P, uint32_t level, uint64_t key) {
+  return part_split(P, level, (uint32_t)hash64(P.H64, 0, key) >> P.bin_shift);
+}
+
 // Block -> (range, chunk): [*begin, *end) of the pass input; false when the
 // block has no chunk (the second pass launches an upper bound of blocks).
-__device__ __forceinline__ bool part_chunk(const PartPass& p, uint32_t blk, uint32_t* seg,
+template <typename T>
+__device__ __forceinline__ bool part_chunk(const PartPassT<T>& p, uint32_t blk, uint32_t* seg,
                                            uint64_t* begin, uint64_t* end) {
   const uint64_t C = p.P.chunk;
   if (p.level == 1) {
@@ -192,11 +205,21 @@ __global__ void part_clear_kernel(PartMeta M, uint32_t fan1, uint32_t levels,
   if (i < 4) status[i] = 0;
 }
 
+// Keys reserved by the tables (the empty marker; for 64-bit keys also the
+// slot-lock key).
+__device__ __forceinline__ bool reserved_key(uint32_t k) { return k == kEmptyKey; }
+__device__ __forceinline__ bool reserved_key(uint64_t k) { return k >= ~0ull - 1; }
+
+// Pairs staged per sub-tile for keys and values of type T (LDS holds two
+// sub-tile arrays of T: 128 KB for 4- and for 8-byte words).
+template <typename T>
+constexpr int sub_tile() { return sizeof(T) == 4 ? kPartSub : kPartSub / 2; }
+
 // Digit counts of the pairs [begin, end) of in_k: stored in hrow (for the
 // scatter's reservations) and added to tot; returns whether the range held
-// the reserved empty key.  Every thread of the block calls it.
-template <typename DigitFn>
-__device__ __forceinline__ bool hist_range(const uint32_t* __restrict__ in_k, uint64_t begin,
+// a reserved key.  Every thread of the block calls it.
+template <typename T, typename DigitFn>
+__device__ __forceinline__ bool hist_range(const T* __restrict__ in_k, uint64_t begin,
                                            uint64_t end, uint32_t fan, DigitFn digit,
                                            uint32_t* __restrict__ hrow,
                                            unsigned long long* __restrict__ tot) {
@@ -206,7 +229,7 @@ __device__ __forceinline__ bool hist_range(const uint32_t* __restrict__ in_k, ui
   bool sentinel = false;
   constexpr int U = 8;
   for (uint64_t base = begin; base < end; base += U * kPassBlock) {
-    uint32_t k[U];
+    T k[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       // branch-free loads: indices past the end re-read the last pair
@@ -217,7 +240,7 @@ __device__ __forceinline__ bool hist_range(const uint32_t* __restrict__ in_k, ui
     for (int j = 0; j < U; ++j) {
       const uint64_t i = base + j * kPassBlock + threadIdx.x;
       if (i < end) {
-        sentinel |= k[j] == kEmptyKey;
+        sentinel |= reserved_key(k[j]);
         atomicAdd(&cnt[digit(k[j])], 1u);
       }
     }
@@ -233,7 +256,8 @@ __device__ __forceinline__ bool hist_range(const uint32_t* __restrict__ in_k, ui
 
 // Digit counts of one chunk: stored per chunk (for the scatter's
 // reservations) and added to the range's digit totals.
-__global__ __launch_bounds__(kPassBlock) void part_hist_kernel(PartPass p) {
+template <typename T>
+__global__ __launch_bounds__(kPassBlock) void part_hist_kernel(PartPassT<T> p) {
   uint32_t seg;
   uint64_t begin, end;
   if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
@@ -242,7 +266,7 @@ __global__ __launch_bounds__(kPassBlock) void part_hist_kernel(PartPass p) {
   const PartPlan& P = p.P;
   const uint32_t level = p.level;
   const bool sentinel = hist_range(p.in_k, begin, end, p.fan,
-                                   [&](uint32_t k) { return part_digit(P, level, k); }, h, tot);
+                                   [&](T k) { return part_digit(P, level, k); }, h, tot);
   if (level == 1 && sentinel) atomicOr(p.status, kFlagSentinel);
 }
 
@@ -297,16 +321,17 @@ __global__ __launch_bounds__(kPartBlock) void part_scan2_kernel(PartPlan P, Part
 // current one is ranked, so they overlap the on-chip work.  Positions are
 // below 2^32 (the partitioned path takes fewer than 2^32 pairs).  Every
 // thread of the block calls it.
-template <typename DigitFn>
-__device__ __forceinline__ void scatter_range(const uint32_t* __restrict__ in_k,
-                                              const uint32_t* __restrict__ in_v, uint64_t begin,
+template <typename T, typename DigitFn>
+__device__ __forceinline__ void scatter_range(const T* __restrict__ in_k,
+                                              const T* __restrict__ in_v, uint64_t begin,
                                               uint64_t end, uint32_t fan, DigitFn digit,
                                               const uint32_t* __restrict__ hrow,
                                               unsigned long long* __restrict__ cur,
-                                              uint32_t* __restrict__ out_k,
-                                              uint32_t* __restrict__ out_v) {
-  __shared__ uint32_t sk[kPartSub];
-  __shared__ uint32_t sv[kPartSub];
+                                              T* __restrict__ out_k, T* __restrict__ out_v) {
+  constexpr int SUB = sub_tile<T>();
+  constexpr int PER = SUB / kPassBlock;
+  __shared__ T sk[SUB];
+  __shared__ T sv[SUB];
   __shared__ uint32_t cnt[kMaxFan];
   __shared__ uint32_t start[kMaxFan];
   __shared__ uint32_t run[kMaxFan];
@@ -319,28 +344,28 @@ __device__ __forceinline__ void scatter_range(const uint32_t* __restrict__ in_k,
   // those copies are never ranked), so the compiler can leave the next
   // sub-tile's loads in flight while the current one is ranked.
   const uint64_t last = end - 1;
-  uint32_t k[kPartPer], v[kPartPer];
+  T k[PER], v[PER];
 #pragma unroll
-  for (int j = 0; j < kPartPer; ++j) {
+  for (int j = 0; j < PER; ++j) {
     const uint64_t i = begin + j * kPassBlock + threadIdx.x;
     k[j] = in_k[i < end ? i : last];
     v[j] = in_v[i < end ? i : last];
   }
-  for (uint64_t sub = begin; sub < end; sub += kPartSub) {
-    uint32_t nk[kPartPer], nv[kPartPer];
+  for (uint64_t sub = begin; sub < end; sub += SUB) {
+    T nk[PER], nv[PER];
 #pragma unroll
-    for (int j = 0; j < kPartPer; ++j) {
-      const uint64_t i = sub + kPartSub + j * kPassBlock + threadIdx.x;
+    for (int j = 0; j < PER; ++j) {
+      const uint64_t i = sub + SUB + j * kPassBlock + threadIdx.x;
       nk[j] = in_k[i < end ? i : last];
       nv[j] = in_v[i < end ? i : last];
     }
     for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) cnt[d] = 0;
     __syncthreads();
     // rank within the digit (< 2^14) and digit (< 2^10) share a register
-    static_assert(kPartSub <= (1 << 22) && kMaxFan <= 1024, "rank and digit packing");
-    uint32_t rd[kPartPer];
+    static_assert(SUB <= (1 << 22) && kMaxFan <= 1024, "rank and digit packing");
+    uint32_t rd[PER];
 #pragma unroll
-    for (int j = 0; j < kPartPer; ++j) {
+    for (int j = 0; j < PER; ++j) {
       const uint64_t i = sub + j * kPassBlock + threadIdx.x;
       if (i < end) {
         const uint32_t d = digit(k[j]);
@@ -350,7 +375,7 @@ __device__ __forceinline__ void scatter_range(const uint32_t* __restrict__ in_k,
     __syncthreads();
     block_exclusive_scan<kPassBlock, uint32_t>(cnt, start, fan, wt);
 #pragma unroll
-    for (int j = 0; j < kPartPer; ++j) {
+    for (int j = 0; j < PER; ++j) {
       const uint64_t i = sub + j * kPassBlock + threadIdx.x;
       if (i < end) {
         const uint32_t pos = start[rd[j] & 1023u] + (rd[j] >> 10);
@@ -359,14 +384,14 @@ __device__ __forceinline__ void scatter_range(const uint32_t* __restrict__ in_k,
       }
     }
     __syncthreads();
-    const uint32_t count = end - sub < (uint64_t)kPartSub ? (uint32_t)(end - sub) : kPartSub;
+    const uint32_t count = end - sub < (uint64_t)SUB ? (uint32_t)(end - sub) : SUB;
     // fixed trip count (no inner loop), so the prefetched loads stay in
     // flight across the stores
 #pragma unroll
-    for (int j = 0; j < kPartPer; ++j) {
+    for (int j = 0; j < PER; ++j) {
       const uint32_t i = j * kPassBlock + threadIdx.x;
       if (i < count) {
-        const uint32_t key = sk[i];
+        const T key = sk[i];
         const uint32_t d = digit(key);                        // recomputed, not stored
         const uint32_t dst = run[d] + (i - start[d]);
         out_k[dst] = key;
@@ -377,14 +402,15 @@ __device__ __forceinline__ void scatter_range(const uint32_t* __restrict__ in_k,
     for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) run[d] += cnt[d];
     // the next sub-tile's first barrier orders these updates before use
 #pragma unroll
-    for (int j = 0; j < kPartPer; ++j) {
+    for (int j = 0; j < PER; ++j) {
       k[j] = nk[j];
       v[j] = nv[j];
     }
   }
 }
 
-__global__ __launch_bounds__(kPassBlock, kScatterBlocksPerCU) void part_scatter_kernel(PartPass p) {
+template <typename T>
+__global__ __launch_bounds__(kPassBlock, kScatterBlocksPerCU) void part_scatter_kernel(PartPassT<T> p) {
   uint32_t seg;
   uint64_t begin, end;
   if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
@@ -393,7 +419,7 @@ __global__ __launch_bounds__(kPassBlock, kScatterBlocksPerCU) void part_scatter_
   const PartPlan& P = p.P;
   const uint32_t level = p.level;
   scatter_range(p.in_k, p.in_v, begin, end, p.fan,
-                [&](uint32_t k) { return part_digit(P, level, k); }, h, cur, p.out_k, p.out_v);
+                [&](T k) { return part_digit(P, level, k); }, h, cur, p.out_k, p.out_v);
 }
 
 struct BinArgs {

@@ -112,16 +112,18 @@ __device__ __forceinline__ uint32_t next_bucket64(const Hash64& H, uint64_t key,
 
 enum : uint32_t { kWRead = 0, kWWalk = 1, kWEvict = 2 };
 
-// W lanes per tile, one 16-byte slot per lane: B = W = 8 slots per bucket.
-template <int W>
-__global__ __launch_bounds__(kBlock) void wide_build_kernel(WideBuildArgs g) {
+// Inserts the pairs [r.cursor, r.end) of g.keys / g.vals (one wave's range;
+// the whole wave calls it).  W lanes per tile, one 16-byte slot per lane:
+// B = W = 8 slots per bucket.  EVICTED: each pair was evicted from its
+// first bucket H_0 (one exchange made) and continues at the next one.
+// Bucket reads are added to *probes; returns the lane's status flags.
+template <int W, bool EVICTED>
+__device__ __forceinline__ uint32_t wide_build_range(const WideBuildArgs& g, Range r, uint32_t rng,
+                                                     uint32_t* probes) {
   constexpr int B = W;
   const uint32_t lane = __lane_id();
   const uint32_t tb = lane & ~(uint32_t)(W - 1);
   const uint32_t lt = lane & (uint32_t)(W - 1);
-  const Range r = wave_range(g.n);
-  const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t rng = g.rng_seed ^ (uint32_t)(gtid * 0x9E3779B9ull) ^ (uint32_t)(gtid >> 32);
   if (rng == 0) rng = 0x2545F491u;
 
   Feed64 fk, fv;
@@ -148,6 +150,10 @@ __global__ __launch_bounds__(kBlock) void wide_build_kernel(WideBuildArgs g) {
         val = v_new;
         bucket = (uint32_t)hash64(g.H, 0, key);
         chain = 0;
+        if constexpr (EVICTED) {
+          bucket = next_bucket64(g.H, key, bucket);
+          chain = 1;
+        }
         attempts = 0;
         phase = kWRead;
       }
@@ -159,6 +165,7 @@ __global__ __launch_bounds__(kBlock) void wide_build_kernel(WideBuildArgs g) {
 
     // Tile read: lane lt loads slot lt (key and value) of each bucket.
     const uint64_t rd = ballot(active && phase == kWRead);
+    *probes += (uint32_t)((rd >> lane) & 1ull);
     uint64_t dk[W];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
@@ -240,6 +247,14 @@ __global__ __launch_bounds__(kBlock) void wide_build_kernel(WideBuildArgs g) {
       }
     }
   }
+  return flags;
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void wide_build_kernel(WideBuildArgs g) {
+  uint32_t probes = 0;
+  const uint32_t flags = wide_build_range<W, false>(g, wave_range(g.n), g.rng_seed ^ lane_salt(),
+                                                    &probes);
   if (flags) atomicOr(g.status, flags);
 }
 

@@ -80,3 +80,114 @@ def test_wide_reserved_keys_rejected_and_contention():
         assert oracle.check64(p, t.download(), keys, vals)[0] == 0
         check(t, keys, vals, datagen.mixed_queries(n, 4 * n, 0.5, 6, wide=True))
         t.close()
+
+
+def build_mode64(n, lf, seed, mode, tries=8):
+    import paper_2108_07232_amd as bht
+    keys, vals = datagen.unique_keys64(n, seed), datagen.values64(n, seed)
+    for s in range(tries):
+        p = oracle.params_for("bcht", n, lf, seed * 100 + s, b=8, wide=True)
+        t = bht.Table(p.m * p.b, 8, "bcht", p.a, p.c, key_bits=64, rng_seed=p.rng_seed,
+                      max_chain=p.max_chain, build_mode=mode)
+        st = t.build(dev(keys), dev(vals))
+        if st == bht.BHT_OK:
+            return t, p, keys, vals
+        assert st == bht.BHT_ERR_BUILD_FAILED, bht.bht_status_string(st)
+        t.close()
+    pytest.fail("no successful 64-bit %s build" % mode)
+
+
+def plan_levels64(m):
+    """Radix passes the library plans for m buckets of 8 16-byte slots."""
+    return 1 if -(-m // 512) <= 1024 else 2
+
+
+@pytest.mark.parametrize("n,lf", [(1 << 20, 0.9), (100003, 0.95), (50000, 0.98), (3000, 0.9),
+                                  (1, 0.5), (9, 0.9), (1 << 18, 0.85)])
+def test_wide_partitioned_build(n, lf):
+    """Partitioned 64-bit build (radix passes, placement in LDS with evictions
+    in ranked rounds, overflow insertion): valid layout, exact lookups, and
+    the on-chip eviction count equals the first-bucket overflow."""
+    import paper_2108_07232_amd as bht
+    print("wide partitioned n=%d lf=%g" % (n, lf), flush=True)
+    t, p, keys, vals = build_mode64(n, lf, 7, "partitioned")
+    code, msg = oracle.check64(p, t.download(), keys, vals)
+    assert code == 0, msg
+    check(t, keys, vals, datagen.mixed_queries(n, max(2 * n, 64), 0.5, 7, wide=True))
+    h0 = oracle.hash64_many(p.a[0], p.c[0], keys, p.m)
+    counts = np.bincount(h0.astype(np.int64), minlength=p.m)
+    part, evicted, probes = bht.bht_build_stats(t.handle)
+    assert part and evicted == int(np.maximum(counts - 8, 0).sum())
+    assert probes >= evicted
+    t.close()
+
+
+def test_wide_partitioned_two_passes():
+    """4,500,000 pairs at load 0.9: 1,221 bins of 512 buckets, two radix
+    passes (the first through the slot array)."""
+    n = 4_500_000
+    print("wide partitioned two-pass n=%d" % n, flush=True)
+    t, p, keys, vals = build_mode64(n, 0.9, 8, "partitioned")
+    assert plan_levels64(p.m) == 2
+    code, msg = oracle.check64(p, t.download(), keys, vals)
+    assert code == 0, msg
+    check(t, keys, vals, datagen.mixed_queries(n, 1 << 21, 0.5, 8, wide=True))
+    t.close()
+
+
+def test_wide_build_modes_agree():
+    """Default, concurrent and partitioned 64-bit builds of 2^20 pairs give
+    valid layouts and identical lookups; the default takes the partitioned
+    path at this size."""
+    import torch
+    import paper_2108_07232_amd as bht
+    n = 1 << 20
+    keys, vals = datagen.unique_keys64(n, 9), datagen.values64(n, 9)
+    p = oracle.params_for("bcht", n, 0.9, 900, b=8, wide=True)
+    q = datagen.mixed_queries(n, n, 0.5, 9, wide=True)
+    results = []
+    for mode in ("auto", "concurrent", "partitioned"):
+        t = bht.Table(p.m * p.b, 8, "bcht", p.a, p.c, key_bits=64, rng_seed=p.rng_seed,
+                      build_mode=mode)
+        assert t.build(dev(keys), dev(vals)) == bht.BHT_OK
+        assert oracle.check64(p, t.download(), keys, vals)[0] == 0
+        assert bht.bht_build_stats(t.handle)[0] == (mode != "concurrent")
+        v, f = t.find(dev(q))
+        torch.cuda.synchronize()
+        results.append((host_u64(v), host_u8(f)))
+        t.close()
+    for v, f in results[1:]:
+        np.testing.assert_array_equal(v, results[0][0])
+        np.testing.assert_array_equal(f, results[0][1])
+
+
+def test_wide_partitioned_crowded_bucket_and_status_paths():
+    """Keys that all share one first bucket (H_0 = k mod m for a = 1, c = 0):
+    one bin takes 6,000 pairs, 8 stay and the rest leave through thousands of
+    ranked eviction rounds.  Reserved keys are refused, and one hash for all
+    three choices fails the build instead of looping."""
+    import paper_2108_07232_amd as bht
+    n, m = 6000, 4000                       # 32,000 slots, load 0.19
+    keys = np.arange(1, n + 1, dtype=np.uint64) * np.uint64(m)
+    vals = datagen.values64(n, 10)
+    a, c = datagen.hash_constants64(10, 3)
+    a, c = [1] + [int(x) for x in a[1:]], [0] + [int(x) for x in c[1:]]
+    p = oracle.Params(scheme="bcht", b=8, m=m, h=3, a=a, c=c)
+    t = bht.Table(m * 8, 8, "bcht", a, c, key_bits=64, build_mode="partitioned")
+    assert t.build(dev(keys), dev(vals)) == bht.BHT_OK
+    assert oracle.check64(p, t.download(), keys, vals)[0] == 0
+    check(t, keys, vals, datagen.mixed_queries(n, 2 * n, 0.5, 10, wide=True))
+    t.close()
+    n = 1 << 16
+    keys, vals = datagen.unique_keys64(n, 12), datagen.values64(n, 12)
+    p = oracle.params_for("bcht", n, 0.9, 12, b=8, wide=True)
+    for bad in ((1 << 64) - 1, (1 << 64) - 2):
+        k = keys.copy()
+        k[n // 2] = bad
+        t = bht.Table(p.m * 8, 8, "bcht", p.a, p.c, key_bits=64, build_mode="partitioned")
+        assert t.build(dev(k), dev(vals)) == bht.BHT_ERR_SENTINEL_KEY
+        t.close()
+    same = [int(p.a[0])] * 3, [int(p.c[0])] * 3
+    t = bht.Table(p.m * 8, 8, "bcht", same[0], same[1], key_bits=64, build_mode="partitioned")
+    assert t.build(dev(keys), dev(vals)) == bht.BHT_ERR_BUILD_FAILED
+    t.close()
