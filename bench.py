@@ -38,6 +38,8 @@ def parse():
                              "success"],
                     help="bcht: the headline BCHT workload; schemes: the comparison of "
                          "BCHT, BP2HT, two-level iceberg, 1CHT and 64-bit BCHT")
+    ap.add_argument("--only", default=None,
+                    help="schemes workload: comma-separated scheme names to run (default all)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--log2n", type=int, default=28)
@@ -226,7 +228,10 @@ def run_schemes(args):
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
     results = {}
+    only = set(args.only.split(",")) if args.only else None
     for name, scheme, b, h, lf0, b2, wide in SCHEME_CONFIGS:
+        if only is not None and name not in only:
+            continue
         log("scheme %s: generating 2^%d inputs" % (name, args.log2n))
         if wide:
             keys, vals = datagen.unique_keys64(n, args.seed), datagen.values64(n, args.seed)
@@ -293,11 +298,30 @@ def run_schemes(args):
                  "build_failures": failures + timed_failures,
                  "buckets": table.info[0], "bucket_slots": b, "secondary_bucket_slots": b2,
                  "hashes": h, "key_bits": 64 if wide else 32}
+        part, evicted, ovf_probes = bht.bht_build_stats(table.handle)
+        entry["build_path"] = "partitioned" if part else "concurrent"
+        if part:
+            entry["evicted_per_key"] = round(evicted / n, 5)
+            entry["overflow_probes_per_evicted"] = round(ovf_probes / max(evicted, 1), 4)
+            # the same table built by the concurrent kernel, for comparison
+            bht.bht_set_tuning(table.handle, build_mode=bht.BUILD_MODES["concurrent"])
+            times = []
+            for _ in range(args.steps):
+                if table.build(d_keys, d_vals) == bht.BHT_OK:
+                    times.append(bht.bht_kernel_ms(table.handle)[0])
+            bht.bht_set_tuning(table.handle, build_mode=bht.BUILD_MODES["auto"])
+            while table.build(d_keys, d_vals) != bht.BHT_OK:
+                hc = datagen.hash_constants64 if wide else datagen.hash_constants
+                a, c = hc(seed, h)
+                seed += 7919
+                bht.bht_reseed(table.handle, bht.make_params(
+                    a, c, key_bits=64 if wide else 32, rng_seed=datagen.rng_seed(seed),
+                    iht_threshold=b if b2 else 0, iht_secondary_b=b2, iht_secondary_m=table.m2))
+            if times:
+                avg = float(np.mean(times))
+                entry["build_concurrent_ms"] = round(avg, 4)
+                entry["build_concurrent_gkeys_s"] = round(n / (avg * 1e-3) / 1e9, 4)
         if not wide:
-            part, evicted, ovf_probes = bht.bht_build_stats(table.handle)
-            entry["build_path"] = "partitioned" if part else "concurrent"
-            if part:
-                entry["evicted_per_key"] = round(evicted / n, 5)
             # probe averages from the instrumented kernels (untimed runs)
             total = torch.zeros(1, dtype=torch.int64, device=dev)
             st = bht.bht_build_counted(table.handle, d_keys, d_vals, total)
