@@ -161,6 +161,43 @@ def cpu_baseline(args, n_s):
           "find_neg": datagen.mixed_queries(n_s, n_s, 0.0, args.seed),
           "find_mix": datagen.mixed_queries(n_s, n_s, 0.5, args.seed)}
     params = None
+    # one thread pinned to one core (this thread only; the GPU is idle here)
+    allowed = os.sched_getaffinity(0)
+    core = min(allowed)
+    os.sched_setaffinity(0, {core})
+    try:
+        times, probes, params = _cpu_runs(args, n_s, keys, vals, qs)
+    finally:
+        os.sched_setaffinity(0, allowed)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    total = sum(times.values())
+    return {
+        "value": round(4 * n_s / total / 1e9, 6),
+        "unit": "Gkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "2^%d keys at LF %g (BCHT b=%d h=3), build + 2^%d queries at 100/0/50%% "
+                  "positive, serial C oracle, one thread" % (args.cpu_log2n, args.lf, args.bucket,
+                                                           args.cpu_log2n),
+        "pinned_core": core,
+        "host_cpu": model,
+        "host_logical_cpus": os.cpu_count(),
+        "seconds": {k: round(v, 3) for k, v in times.items()},
+        "rates_gkeys_s": {k: round(n_s / v / 1e9, 6) for k, v in times.items()},
+    }, probes
+
+
+def _cpu_runs(args, n_s, keys, vals, qs):
+    import oracle
+    params = None
     for s in range(50):
         params = oracle.params_for("bcht", n_s, args.lf, args.seed + 1000 * s, b=args.bucket)
         t0 = time.perf_counter()
@@ -175,18 +212,7 @@ def cpu_baseline(args, n_s):
         _, _, pr, _ = oracle.find32(params, table, q)
         times[name] = time.perf_counter() - t0
         probes[name.replace("find_", "")] = pr / n_s
-    total = sum(times.values())
-    return {
-        "value": round(4 * n_s / total / 1e9, 6),
-        "unit": "Gkeys/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": "2^%d keys at LF %g (BCHT b=%d h=3), build + 2^%d queries at 100/0/50%% "
-                  "positive, serial C oracle, one thread" % (args.cpu_log2n, args.lf, args.bucket,
-                                                           args.cpu_log2n),
-        "seconds": {k: round(v, 3) for k, v in times.items()},
-        "rates_gkeys_s": {k: round(n_s / v / 1e9, 6) for k, v in times.items()},
-    }, probes
+    return times, probes, params
 
 
 SCHEME_CONFIGS = [
@@ -1124,6 +1150,7 @@ def main():
     ceilings = measure_ceilings(bht, table, torch, stream) if not args.no_ceilings else None
 
     kernel_ms = {k: float(np.mean(v)) for k, v in rec.items()}
+    step_ms = rec
     cpu = None
     probes = None
     if not args.no_cpu_baseline:
@@ -1139,7 +1166,9 @@ def main():
     kernels = {}
     for name in ("build", "find_pos", "find_neg", "find_mix"):
         ms = kernel_ms[name]
-        entry = {"ms": round(ms, 4), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 4)}
+        entry = {"ms": round(ms, 4), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 4),
+                 "ms_median": round(float(np.median(step_ms[name])), 4),
+                 "ms_min": round(float(np.min(step_ms[name])), 4)}
         if bytes_per:
             gbs = bytes_per[name] * n / (ms * 1e-3) / 1e9
             entry.update({"bytes_per_key": round(bytes_per[name], 2), "achieved_gbs": round(gbs, 1),
@@ -1150,9 +1179,9 @@ def main():
     if bytes_per:
         ach = kernels[dominant]["achieved_gbs"]
         traffic = None
-        rec = recorded_traffic()
-        if rec and rec.get("n") == n and dominant in rec:
-            traffic = rec[dominant]
+        recorded = recorded_traffic()
+        if recorded and recorded.get("n") == n and dominant in recorded:
+            traffic = recorded[dominant]
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic}
         if traffic:
