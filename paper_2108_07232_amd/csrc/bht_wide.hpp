@@ -258,14 +258,37 @@ __global__ __launch_bounds__(kBlock) void wide_build_kernel(WideBuildArgs g) {
   if (flags) atomicOr(g.status, flags);
 }
 
-// Cuckoo query with early exit, chunk schedule (as the 32-bit kernel).
+// Bit 0 of every W-lane group of a 64-bit lane mask set iff some bit of the
+// group is (wave-uniform: scalar instructions).
+template <int W>
+__device__ __forceinline__ uint64_t group_any(uint64_t x) {
+  uint64_t low = 0;
+#pragma unroll
+  for (int t = 0; t < 64; t += W) low |= 1ull << t;
+#pragma unroll
+  for (int sh = 1; sh < W; sh <<= 1) x |= x >> sh;
+  return x & low;
+}
+
+// Cuckoo query with early exit, chunk schedule (as the 32-bit kernel), with
+// the per-slice work kept to compares: the tile's queries are exchanged
+// once per chunk and its bucket indices once per round; a slice whose owner
+// is closed is not loaded; the tile reductions of the ballots are scalar
+// (bit t*W + j of hacc / eacc is tile t's answer for its lane j); the one
+// matching lane of a tile (keys are unique) leaves the value in the owner's
+// LDS word.
 template <int W>
 __global__ __launch_bounds__(kBlock) void wide_find_chunk_kernel(WideFindArgs g) {
   constexpr int B = W;
   const uint32_t lane = __lane_id();
   const uint32_t tb = lane & ~(uint32_t)(W - 1);
   const uint32_t lt = lane & (uint32_t)(W - 1);
+  __shared__ uint64_t vlds[kBlock];
+  uint64_t* const vbuf = vlds + (threadIdx.x & ~63u);
   const Range r = wave_range(g.n);
+  u64x2 d[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) d[j] = u64x2{kEmpty64, kEmpty64};
   uint64_t q_next = (r.cursor + lane < r.end) ? g.queries[r.cursor + lane] : kEmpty64;
   for (uint64_t base = r.cursor; base < r.end; base += 64) {
     const uint64_t idx = base + lane;
@@ -275,36 +298,36 @@ __global__ __launch_bounds__(kBlock) void wide_find_chunk_kernel(WideFindArgs g)
     bool open = valid && q < kBusy64;
     uint64_t out = kEmpty64;
     uint8_t found = 0;
+    uint64_t qt[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) qt[j] = shfl64(q, tb + j);
     for (uint32_t round = 0; round < g.H.h; ++round) {
       const uint64_t om = ballot(open);
       if (om == 0) break;
       const uint32_t bucket = open ? (uint32_t)hash64(sel4(g.H.a, round), sel4(g.H.c, round), q,
                                                       g.H.M, g.H.m)
                                    : 0u;
-      bool hit = false, room = false;
-      uint64_t value = kEmpty64;
+      uint32_t bj[W];
+#pragma unroll
+      for (int j = 0; j < W; ++j) bj[j] = shfl32(bucket, tb + j);
+      const uint32_t own = (uint32_t)(om >> tb);
+#pragma unroll
+      for (int j = 0; j < W; ++j)
+        if ((own >> j) & 1u) d[j] = reinterpret_cast<const u64x2*>(g.slots)[(uint64_t)bj[j] * B + lt];
+      uint64_t hacc = 0, eacc = 0;
 #pragma unroll
       for (int j = 0; j < W; ++j) {
-        const uint32_t bj = shfl32(bucket, tb + j);
-        u64x2 s = {kEmpty64, kEmpty64};
-        if ((om >> (tb + j)) & 1ull)
-          s = reinterpret_cast<const u64x2*>(g.slots)[(uint64_t)bj * B + lt];
-        const uint64_t qj = shfl64(q, tb + j);
-        const uint64_t hm = tile_bits<W>(ballot(s.x == qj), tb);
-        const uint64_t em = tile_bits<W>(ballot(s.x == kEmpty64), tb);
-        const uint64_t v = shfl64(s.y, tb + (hm ? (uint32_t)__builtin_ctzll(hm) : 0u));
-        if (lt == (uint32_t)j) {
-          hit = hm != 0;
-          room = em != 0;
-          value = v;
-        }
+        const bool hs = d[j].x == qt[j];
+        if (hs) vbuf[tb + j] = d[j].y;
+        hacc |= group_any<W>(__builtin_amdgcn_ballot_w64(hs)) << j;
+        eacc |= group_any<W>(__builtin_amdgcn_ballot_w64(d[j].x == kEmpty64)) << j;
       }
       if (open) {
-        if (hit) {
-          out = value;
+        if ((hacc >> lane) & 1ull) {
+          out = vbuf[lane];
           found = 1;
           open = false;
-        } else if (room) {
+        } else if ((eacc >> lane) & 1ull) {
           open = false;
         }
       }
