@@ -510,6 +510,51 @@ PartMeta part_meta(const PartLayout& L, char* w) {
   return M;
 }
 
+// Radix passes of a partitioned build: groups the n pairs (keys, vals) by
+// bin into (keys2, vals2), through (mid_k, mid_v) when two passes are
+// planned.  T = key and value word (uint32_t or uint64_t).
+template <typename T>
+void launch_radix(const PartPlan& P, const PartMeta& M, const PartLayout& L, const T* keys,
+                  const T* vals, uint64_t n, T* mid_k, T* mid_v, T* keys2, T* vals2,
+                  uint32_t* status, hipStream_t st) {
+  void (*hist)(PartPassT<T>);
+  void (*scatter)(PartPassT<T>);
+  if constexpr (sizeof(T) == 4) {
+    hist = part_hist_kernel<uint32_t>;
+    scatter = part_scatter_kernel<uint32_t>;
+  } else {
+    hist = part_hist64_kernel;
+    scatter = part_scatter64_kernel;
+  }
+  part_clear_kernel<<<64, kPartBlock, 0, st>>>(M, P.fan1, P.levels, status);
+  PartPassT<T> p1;
+  p1.in_k = keys;
+  p1.in_v = vals;
+  p1.out_k = P.levels == 1 ? keys2 : mid_k;
+  p1.out_v = P.levels == 1 ? vals2 : mid_v;
+  p1.n = n;
+  p1.level = 1;
+  p1.fan = P.fan1;
+  p1.status = status;
+  p1.P = P;
+  p1.M = M;
+  hist<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
+  part_scan1_kernel<<<1, kPartBlock, 0, st>>>(P, M);
+  scatter<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
+  if (P.levels == 2) {
+    PartPassT<T> p2 = p1;
+    p2.in_k = mid_k;
+    p2.in_v = mid_v;
+    p2.out_k = keys2;
+    p2.out_v = vals2;
+    p2.level = 2;
+    p2.fan = kFan2;
+    hist<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
+    part_scan2_kernel<<<P.fan1, kPartBlock, 0, st>>>(P, M);
+    scatter<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
+  }
+}
+
 // Partitioned build of a 64-bit table (8-slot buckets); library-owned
 // workspace.
 bht_status build64_partitioned(bht_table* t, const uint64_t* keys, const uint64_t* vals,
@@ -528,33 +573,7 @@ bht_status build64_partitioned(bht_table* t, const uint64_t* keys, const uint64_
   uint64_t* mid_v = mid_k + n;
 
   if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
-  part_clear_kernel<<<64, kPartBlock, 0, st>>>(M, P.fan1, P.levels, t->d_status);
-  PartPass64 p1;
-  p1.in_k = keys;
-  p1.in_v = vals;
-  p1.out_k = P.levels == 1 ? keys2 : mid_k;
-  p1.out_v = P.levels == 1 ? vals2 : mid_v;
-  p1.n = n;
-  p1.level = 1;
-  p1.fan = P.fan1;
-  p1.status = t->d_status;
-  p1.P = P;
-  p1.M = M;
-  part_hist64_kernel<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
-  part_scan1_kernel<<<1, kPartBlock, 0, st>>>(P, M);
-  part_scatter64_kernel<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
-  if (P.levels == 2) {
-    PartPass64 p2 = p1;
-    p2.in_k = mid_k;
-    p2.in_v = mid_v;
-    p2.out_k = keys2;
-    p2.out_v = vals2;
-    p2.level = 2;
-    p2.fan = kFan2;
-    part_hist64_kernel<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
-    part_scan2_kernel<<<P.fan1, kPartBlock, 0, st>>>(P, M);
-    part_scatter64_kernel<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
-  }
+  launch_radix<uint64_t>(P, M, L, keys, vals, n, mid_k, mid_v, keys2, vals2, t->d_status, st);
   BinArgs64 ba;
   ba.slots = t->d_slots;
   ba.keys = keys2;
@@ -610,33 +629,7 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
   uint32_t* mid_v = mid_k + n;
 
   if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
-  part_clear_kernel<<<64, kPartBlock, 0, st>>>(M, P.fan1, P.levels, t->d_status);
-  PartPass p1;
-  p1.in_k = keys;
-  p1.in_v = vals;
-  p1.out_k = P.levels == 1 ? keys2 : mid_k;
-  p1.out_v = P.levels == 1 ? vals2 : mid_v;
-  p1.n = n;
-  p1.level = 1;
-  p1.fan = P.fan1;
-  p1.status = t->d_status;
-  p1.P = P;
-  p1.M = M;
-  part_hist_kernel<uint32_t><<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
-  part_scan1_kernel<<<1, kPartBlock, 0, st>>>(P, M);
-  part_scatter_kernel<uint32_t><<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
-  if (P.levels == 2) {
-    PartPass p2 = p1;
-    p2.in_k = mid_k;
-    p2.in_v = mid_v;
-    p2.out_k = keys2;
-    p2.out_v = vals2;
-    p2.level = 2;
-    p2.fan = kFan2;
-    part_hist_kernel<uint32_t><<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
-    part_scan2_kernel<<<P.fan1, kPartBlock, 0, st>>>(P, M);
-    part_scatter_kernel<uint32_t><<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
-  }
+  launch_radix<uint32_t>(P, M, L, keys, vals, n, mid_k, mid_v, keys2, vals2, t->d_status, st);
   BinArgs ba;
   ba.slots = t->d_slots;
   ba.keys = keys2;
