@@ -4,17 +4,25 @@
 //
 // gfx950 has no 128-bit compare-and-swap, so a slot changes hands through
 // its key word, used as a lock: the reserved key BUSY marks a slot whose
-// value word is being replaced.  Every step is an atomic with a return
-// value, performed at the device's coherence point for that address, and
-// the lane waits for each one before the next, so the steps of one slot are
-// ordered without cache-wide release or acquire fences:
-//   claim an empty slot:  CAS key EMPTY -> BUSY, exchange value, exchange key BUSY -> k
+// value word is being replaced.  Every step is a device-scope atomic
+// (compare-and-swap or exchange with a return value, or a device-scope
+// store, which is written through to the level where those atomics are
+// performed), and the lane waits for each one to complete before issuing
+// the next, so the steps of one slot are ordered without cache-wide release
+// or acquire fences:
+//   claim an empty slot:  CAS key EMPTY -> BUSY, store value, store key k
 //   evict a resident:     CAS key k' -> BUSY, exchange value (returns v'),
-//                         exchange key BUSY -> k, carry (k', v')
-// A slot is BUSY only inside one loop iteration of its owner, so a lane that
-// meets BUSY retries on a later iteration; a per-pair attempt cap turns any
-// unforeseen starvation into a reported build failure instead of a hang.
-// Queries run in a later launch and never see BUSY.
+//                         store key k, carry (k', v')
+// Only the lane whose CAS set BUSY writes the slot until its key store
+// releases it, so the releasing stores need no read-modify-write; the two
+// words of a slot also share one cache line and so one memory channel.  A
+// lane whose CAS takes the slot from key k has seen the key store of k's
+// writer, which was issued after that writer's value store completed, so
+// its value exchange returns k's value.  A slot is BUSY only inside one loop
+// iteration of its owner, so a lane that meets BUSY retries on a later
+// iteration; a per-pair attempt cap turns any unforeseen starvation into a
+// reported build failure instead of a hang.  Queries run in a later launch
+// and never see BUSY.
 #pragma once
 #include "bht_kernels.hpp"
 
@@ -33,6 +41,10 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t src) {
 
 __device__ __forceinline__ uint64_t load_key_agent(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wave feed of 64-bit items (same scheme as Feed<uint32_t>).
@@ -209,9 +221,9 @@ __device__ __forceinline__ uint32_t wide_build_range(const WideBuildArgs& g, Ran
       const uint64_t c = cas64(sk, kEmpty64, kBusy64);
       if (c == kEmpty64) {
         wait_memory();
-        xchg64(sk + 1, val);
+        store_agent(sk + 1, val);
         wait_memory();
-        xchg64(sk, key);
+        store_agent(sk, key);
         active = false;
       } else if (++slot == (uint32_t)B) {
         // every slot is taken: evict at a random slot whose key is learned
@@ -235,7 +247,7 @@ __device__ __forceinline__ uint32_t wide_build_range(const WideBuildArgs& g, Ran
           wait_memory();
           const uint64_t old_v = xchg64(sk + 1, val);
           wait_memory();
-          xchg64(sk, key);
+          store_agent(sk, key);
           key = expect;
           val = old_v;
           bucket = next_bucket64(g.H, key, bucket);
