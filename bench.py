@@ -1186,6 +1186,14 @@ def main():
             entry.update({"bytes_per_key": round(bytes_per[name], 2), "achieved_gbs": round(gbs, 1),
                           "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
         kernels[name] = entry
+    if probes and build_stats:
+        # the same rate priced with the concurrent insertion's bytes per key
+        # (the paper's cost model), which the partitioned order avoids moving
+        paper = algorithmic_bytes(probes)["build"] + 8 * build_stats["slots_per_key"]
+        gbs = paper * n / (kernel_ms["build"] * 1e-3) / 1e9
+        kernels["build"].update({"paper_model_bytes_per_key": round(paper, 2),
+                                 "paper_model_gbs": round(gbs, 1),
+                                 "paper_model_frac": round(gbs / HBM_PEAK_GBS, 4)})
     dominant = max(("build", "find_pos", "find_neg", "find_mix"), key=lambda k: kernel_ms[k])
     roofline = None
     if bytes_per:
