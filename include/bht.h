@@ -231,8 +231,9 @@ bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint6
  * candidate buckets of a query are read at once, Section II-A's parallel
  * query: one memory latency per query instead of up to h, at h probes per
  * query; results are identical).  grid_blocks: blocks of 256 threads per launch,
- * 0 = as many as the device keeps resident.  build_mode (BCHT, CHT1 and
- * the 64-bit table; 64-bit tables take tile_width 8 and ignore the rest):
+ * 0 = as many as the device keeps resident.  build_mode (BCHT, CHT1, IHT
+ * and the 64-bit table; 64-bit tables take tile_width 8 and ignore the
+ * rest):
  * BHT_BUILD_CONCURRENT inserts every pair with the concurrent cuckoo
  * kernel (Section V-B); BHT_BUILD_PARTITIONED first groups the pairs by the
  * region of their first bucket (two streaming radix passes), places each
@@ -241,8 +242,12 @@ bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint6
  * bucket was full: the serial algorithm of Section III-A in one particular
  * insertion order, so layouts obey the same invariants.  It allocates a
  * library-owned workspace of about 8 bytes per pair on first use (kept
- * until bht_destroy).  BHT_BUILD_AUTO partitions builds of at least 2^18
- * pairs into tables whose memory the library owns (bht_create).
+ * until bht_destroy).  Iceberg tables (Section III-C) take the same path
+ * with primaries filled on chip up to iht_threshold pairs and the rest
+ * inserted at their secondary choices (the threshold rule in one serial
+ * order).  BHT_BUILD_AUTO partitions builds of at least 2^18 pairs (2^26
+ * for two-level iceberg tables, never one-level ones) into tables whose
+ * memory the library owns (bht_create).
  * iht_early_exit (iceberg tables only, else UNSUPPORTED): 1 makes a find
  * stop after a miss in a primary bucket that holds fewer than
  * iht_threshold keys, which proves absence because a key goes to a

@@ -19,6 +19,7 @@
 #include "bht_batch.hpp"
 #include "bht_partition.hpp"
 #include "bht_wide_partition.hpp"
+#include "bht_iceberg_partition.hpp"
 
 using namespace bht;
 
@@ -360,16 +361,42 @@ Hash32 secondary_hash(const bht_table* t) {
 // Smallest build that takes the partitioned path by default: below it the
 // fixed cost of its eight launches outweighs the saved atomics.
 constexpr uint64_t kPartMinKeys = 1ull << 18;
+// The same for two-level iceberg tables, whose overflow phase runs with
+// limited concurrency (see build32_partitioned): below about 2^25 pairs
+// the concurrent build is faster.  One-level iceberg tables take the
+// partitioned path only when asked: near their load limit it fails more
+// often than the concurrent build.
+constexpr uint64_t kIcebergPartMinKeys = 1ull << 26;
 
 struct PartKernels {
   const void* place;
   const void* overflow;
+  bool iceberg;          // placement without eviction, iceberg overflow insertion
 };
 
-bool part_kernels(uint32_t b, uint32_t w, PartKernels* k) {
+// Placement and overflow kernels of a partitioned build of table t (tile
+// width w); false when the table's scheme or geometry has none.
+bool part_kernels(const bht_table* t, uint32_t w, PartKernels* k) {
+  const uint32_t b = t->b;
+  if (t->scheme == BHT_IHT) {
+    const uint32_t b2 = t->params.iht_secondary_b;
+#define BHT_ICASE(B_, B2_, W_)                                                     \
+  if (b == B_ && b2 == B2_ && w == W_) {                                           \
+    *k = {(const void*)bin_place_kernel<B_, false>,                                \
+          (const void*)iceberg_overflow_kernel<B_, B2_, W_>, true};                \
+    return true;                                                                   \
+  }
+    BHT_ICASE(16, 0, 8)
+    BHT_ICASE(16, 8, 8)
+    BHT_ICASE(32, 0, 16)
+    BHT_ICASE(32, 8, 16)
+#undef BHT_ICASE
+    return false;
+  }
+  if (t->scheme != BHT_BCHT && t->scheme != BHT_CHT1) return false;
 #define BHT_PCASE(B_, W_)                                                          \
   if (b == B_ && w == W_) {                                                        \
-    *k = {(const void*)bin_place_kernel<B_>, (const void*)overflow_build_kernel<B_, W_>}; \
+    *k = {(const void*)bin_place_kernel<B_>, (const void*)overflow_build_kernel<B_, W_>, false}; \
     return true;                                                                   \
   }
   BHT_PCASE(1, 1)
@@ -456,15 +483,25 @@ PartLayout part_layout(const PartPlan& P, uint64_t n, uint32_t word_bytes = 4) {
   return L;
 }
 
+// Schemes with a partitioned build: the cuckoo tables, and iceberg tables
+// whose primaries take at least one pair.
+bool partition_scheme(const bht_table* t) {
+  if (t->scheme == BHT_BCHT || t->scheme == BHT_CHT1) return true;
+  return t->scheme == BHT_IHT && t->key_bits == 32 && t->params.iht_threshold > 0;
+}
+
 bool use_partitioned(const bht_table* t, uint64_t n, bool counting) {
   if (counting || n == 0 || n >= (1ull << 32)) return false;
-  if (t->scheme != BHT_BCHT && t->scheme != BHT_CHT1) return false;
+  if (!partition_scheme(t)) return false;
   if (t->key_bits == 64 && t->b != 8) return false;
   if (t->build_mode == BHT_BUILD_CONCURRENT) return false;
   PartPlan P;
   if (!part_plan(t, n, &P)) return false;
   if (t->build_mode == BHT_BUILD_PARTITIONED) return true;
-  return n >= kPartMinKeys && t->owns_memory;
+  if (!t->owns_memory) return false;
+  if (t->scheme == BHT_IHT)
+    return t->params.iht_secondary_b != 0 && n >= kIcebergPartMinKeys;
+  return n >= kPartMinKeys;
 }
 
 // *w <- the workspace for layout L: the caller's ws (of ws_bytes), or, when
@@ -614,7 +651,7 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
   PartPlan P;
   if (!part_plan(t, n, &P)) return fail(BHT_ERR_UNSUPPORTED, "table too large to partition");
   PartKernels K;
-  if (!part_kernels(t->b, t->tile, &K))
+  if (!part_kernels(t, t->tile, &K))
     return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
   const PartLayout L = part_layout(P, n);
   char* w = nullptr;
@@ -624,12 +661,18 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
   uint32_t* keys2 = reinterpret_cast<uint32_t*>(w + L.keys);
   uint32_t* vals2 = reinterpret_cast<uint32_t*>(w + L.vals);
   // With two passes the first pass writes into the table's slot array,
-  // which holds at least n pairs and is rewritten whole by the placement.
+  // which holds at least n pairs and is rewritten whole by the placement
+  // (and a two-level iceberg table's secondary array by the reset below).
   uint32_t* mid_k = reinterpret_cast<uint32_t*>(t->d_slots);
   uint32_t* mid_v = mid_k + n;
 
   if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
   launch_radix<uint32_t>(P, M, L, keys, vals, n, mid_k, mid_v, keys2, vals2, t->d_status, st);
+  if (uint64_t* sec = secondary_slots(t)) {
+    const uint64_t words = t->params.iht_secondary_m * t->params.iht_secondary_b;
+    const int grid = (int)std::min<uint64_t>((words / 2 + kBlock) / kBlock, 8192);
+    fill_empty_kernel<<<grid, kBlock, 0, st>>>(sec, words, nullptr);
+  }
   BinArgs ba;
   ba.slots = t->d_slots;
   ba.keys = keys2;
@@ -637,25 +680,53 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
   ba.status = t->d_status;
   ba.max_chain = t->params.max_chain;
   ba.rng_seed = t->params.rng_seed;
+  ba.cap = K.iceberg ? std::min(t->params.iht_threshold, t->b) : t->b;
   ba.P = P;
   ba.M = M;
   reinterpret_cast<void (*)(BinArgs)>(const_cast<void*>(K.place))
       <<<P.nbins, kBinBlock, 0, st>>>(ba);
-  OverflowArgs oa;
-  oa.g.slots = t->d_slots;
-  oa.g.keys = keys2;
-  oa.g.vals = vals2;
-  oa.g.n = n;
-  oa.g.status = t->d_status;
-  oa.g.probe_total = nullptr;
-  oa.g.H = P.H;
-  oa.g.max_chain = t->params.max_chain;
-  oa.g.rng_seed = t->params.rng_seed;
-  oa.M = M;
-  oa.nbins = P.nbins;
-  const int og = grid_for(K.overflow, (uint64_t)P.nbins * 64, t->grid_blocks);
-  reinterpret_cast<void (*)(OverflowArgs)>(const_cast<void*>(K.overflow))
-      <<<og, kBlock, 0, st>>>(oa);
+  if (K.iceberg) {
+    IcebergOverflowArgs ia;
+    ia.g.slots = t->d_slots;
+    ia.g.slots2 = secondary_slots(t);
+    ia.g.keys = keys2;
+    ia.g.vals = vals2;
+    ia.g.n = n;
+    ia.g.status = t->d_status;
+    ia.g.probe_total = nullptr;
+    ia.g.H = P.H;
+    ia.g.H2 = secondary_hash(t);
+    ia.g.threshold = t->params.iht_threshold;
+    ia.M = M;
+    ia.nbins = P.nbins;
+    // Secondary choices are made on loads read before the CAS; with many
+    // pairs in flight they choose from the same stale loads and pile into
+    // the same buckets, and near the load limit builds fail that a serial
+    // insertion in the same order completes.  One lane per 32 secondary
+    // buckets keeps the placements in flight to ~3% of those buckets (at
+    // 2^27 pairs, LF 0.86: 6 of 6 builds succeed, 1 of 6 with a full device).
+    const uint64_t sec_buckets = t->params.iht_secondary_b ? t->params.iht_secondary_m : t->m;
+    const uint64_t lanes = std::max<uint64_t>(sec_buckets / 32, 64);
+    const int ig = grid_for(K.overflow, lanes, t->grid_blocks);
+    reinterpret_cast<void (*)(IcebergOverflowArgs)>(const_cast<void*>(K.overflow))
+        <<<ig, kBlock, 0, st>>>(ia);
+  } else {
+    OverflowArgs oa;
+    oa.g.slots = t->d_slots;
+    oa.g.keys = keys2;
+    oa.g.vals = vals2;
+    oa.g.n = n;
+    oa.g.status = t->d_status;
+    oa.g.probe_total = nullptr;
+    oa.g.H = P.H;
+    oa.g.max_chain = t->params.max_chain;
+    oa.g.rng_seed = t->params.rng_seed;
+    oa.M = M;
+    oa.nbins = P.nbins;
+    const int og = grid_for(K.overflow, (uint64_t)P.nbins * 64, t->grid_blocks);
+    reinterpret_cast<void (*)(OverflowArgs)>(const_cast<void*>(K.overflow))
+        <<<og, kBlock, 0, st>>>(oa);
+  }
   HIP_TRY(hipGetLastError());
   if (t->timing) HIP_TRY(hipEventRecord(t->ev[1], st));
   t->build_timed = t->timing;

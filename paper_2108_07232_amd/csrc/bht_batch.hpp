@@ -227,7 +227,8 @@ __global__ __launch_bounds__(kBinBlock) void batch_place_kernel(BatchPartArgs a)
   const uint64_t first = (uint64_t)(g - a.parts[t].bin_off) * R;
   const uint32_t nb = (uint64_t)T.H.m - first < (uint64_t)R ? (uint32_t)(T.H.m - first) : R;
   const uint32_t ovf = place_bin<B>(T.slots, a.keys, a.vals, T.H, R, first, nb, a.bin_start[g],
-                                    a.bin_len[g], T.max_chain, T.rng_seed, g, a.status + t);
+                                    a.bin_len[g], T.max_chain, T.rng_seed, g, (uint32_t)B,
+                                    a.status + t);
   if (threadIdx.x == 0) a.ovf_len[g] = ovf;
 }
 

@@ -429,27 +429,31 @@ struct BinArgs {
   uint32_t* status;
   uint32_t max_chain;
   uint32_t rng_seed;
+  uint32_t cap;                  // pairs a first bucket takes on chip (b; iceberg: t)
   PartPlan P;
   PartMeta M;
 };
 
 // One bin in LDS.  Each pair claims the next slot of its first bucket (a
-// local atomic on the bucket's load).  A pair that finds the bucket full
-// makes the cuckoo step of Section III-A on chip: after a barrier (every
-// claimed slot is then written) it exchanges itself with a random slot of
-// the bucket, and the evicted pair is written to the front of the bin's
-// input range, to continue at its next bucket in the overflow kernel.  The
-// bin's buckets, empty slots included, are then stored whole.  The bin is
-// buckets [first, first + nb) of the table (nb <= R <= slots / B); its pairs
-// are keys/vals[s0, s0 + len).  Returns (in every thread) the number of
-// evicted pairs; raises flags in *status.  Every thread of the block calls it.
-template <int B>
+// local atomic on the bucket's load) while the bucket holds fewer than cap
+// pairs.  EVICT (cuckoo, cap = B): a pair that finds the bucket full makes
+// the cuckoo step of Section III-A on chip: after a barrier (every claimed
+// slot is then written) it exchanges itself with a random slot of the
+// bucket, and the evicted pair is written to the front of the bin's input
+// range, to continue at its next bucket in the overflow kernel.  Without
+// EVICT (iceberg, cap = t, Section III-C) the pair itself goes there, to
+// continue at its secondary choices.  The bin's buckets, empty slots
+// included, are then stored whole.  The bin is buckets [first, first + nb)
+// of the table (nb <= R <= slots / B); its pairs are keys/vals[s0, s0 +
+// len).  Returns (in every thread) the number of pairs written back; raises
+// flags in *status.  Every thread of the block calls it.
+template <int B, bool EVICT = true>
 __device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
                                               uint32_t* __restrict__ keys,
                                               uint32_t* __restrict__ vals, const Hash32& H,
                                               uint32_t R, uint64_t first, uint32_t nb,
                                               uint64_t s0, uint64_t len, uint32_t max_chain,
-                                              uint32_t rng_seed, uint32_t salt,
+                                              uint32_t rng_seed, uint32_t salt, uint32_t cap,
                                               uint32_t* __restrict__ status) {
   constexpr int S = bin_slots<B>();
   constexpr int RMAX = S / B;                    // buckets per bin, at most
@@ -485,7 +489,7 @@ __device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
           flags |= kFlagFailed;
         } else {
           const uint32_t s = atomicAdd(&load[lb], 1u);
-          if (s < (uint32_t)B) tbl[lb * B + s] = ((unsigned long long)v[j] << 32) | k[j];
+          if (s < cap) tbl[lb * B + s] = ((unsigned long long)v[j] << 32) | k[j];
           else full[j] = lb;
         }
       }
@@ -498,7 +502,9 @@ __device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
 #pragma unroll
     for (int j = 0; j < kBinPer; ++j) {
       if (full[j] != ~0u) {
-        if (max_chain == 0) {
+        if constexpr (!EVICT) {
+          full[j] = atomicAdd(&ovf, 1u);
+        } else if (max_chain == 0) {
           flags |= kFlagFailed;
           full[j] = ~0u;
         } else {
@@ -528,15 +534,15 @@ __device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
   return ovf;
 }
 
-template <int B>
+template <int B, bool EVICT = true>
 __global__ __launch_bounds__(kBinBlock) void bin_place_kernel(BinArgs a) {
   const uint32_t R = 1u << a.P.bin_shift;        // buckets per bin of this plan
   const uint32_t bin = blockIdx.x;
   const uint64_t first = (uint64_t)bin * R;
   const uint32_t nb = (uint64_t)a.P.H.m - first < (uint64_t)R ? (uint32_t)(a.P.H.m - first) : R;
   const uint32_t ovf =
-      place_bin<B>(a.slots, a.keys, a.vals, a.P.H, R, first, nb, a.M.bin_start[bin],
-                   a.M.bin_len[bin], a.max_chain, a.rng_seed, bin, a.status);
+      place_bin<B, EVICT>(a.slots, a.keys, a.vals, a.P.H, R, first, nb, a.M.bin_start[bin],
+                          a.M.bin_len[bin], a.max_chain, a.rng_seed, bin, a.cap, a.status);
   if (threadIdx.x == 0) {
     a.M.ovf_len[bin] = ovf;
     if (ovf) atomicAdd(a.status + 1, ovf);       // evicted pairs of the build

@@ -336,14 +336,19 @@ enum : uint32_t { kIcReadP = 0, kIcReadS = 1, kIcWalkP = 2, kIcWalkS1 = 3, kIcWa
 // pair while it holds fewer than t pairs; otherwise the two secondary
 // buckets are read and the less loaded one (ties to s0) takes it, then the
 // other; with both secondaries full the primary is used if it has room.  B2
-// = 0 puts the secondary choices in the primary array (one level).
-template <int B, int B2, int W, bool COUNT>
-__global__ __launch_bounds__(kBlock) void iceberg_build_kernel(SchemeArgs32 g) {
+// = 0 puts the secondary choices in the primary array (one level).  Inserts
+// the pairs [r.cursor, r.end) of g.keys / g.vals (the whole wave calls it).
+// AFTER_PRIMARY: each pair's primary is known to hold t pairs in its first
+// t slots (the partitioned build placed them), so the pair starts at its
+// secondary choices.  Bucket reads are added to *probes_out when COUNT;
+// returns the lane's status flags.
+template <int B, int B2, int W, bool COUNT, bool AFTER_PRIMARY = false>
+__device__ __forceinline__ uint32_t iceberg_build_range(const SchemeArgs32& g, Range r,
+                                                        uint32_t* probes_out) {
   constexpr int BS2 = B2 ? B2 : B;
   const uint32_t lane = __lane_id();
   const uint32_t tb = lane & ~(uint32_t)(W - 1);
   const uint32_t lt = lane & (uint32_t)(W - 1);
-  const Range r = wave_range(g.n);
   uint64_t* const sec = B2 ? g.slots2 : g.slots;
   const Hash32& HS = B2 ? g.H2 : g.H;
   Feed<uint32_t> fk, fv;
@@ -373,6 +378,12 @@ __global__ __launch_bounds__(kBlock) void iceberg_build_kernel(SchemeArgs32 g) {
         val = v_new;
         p = hash32(g.H, 0, key);
         phase = kIcReadP;
+        if constexpr (AFTER_PRIMARY) {
+          lp = t;
+          s0 = hash32(HS, 1, key);
+          s1 = hash32(HS, 2, key);
+          phase = kIcReadS;
+        }
       }
     }
     if (ballot(active) == 0) {
@@ -443,6 +454,14 @@ __global__ __launch_bounds__(kBlock) void iceberg_build_kernel(SchemeArgs32 g) {
       }
     }
   }
+  if (COUNT) *probes_out += probes;
+  return flags;
+}
+
+template <int B, int B2, int W, bool COUNT>
+__global__ __launch_bounds__(kBlock) void iceberg_build_kernel(SchemeArgs32 g) {
+  uint32_t probes = 0;
+  const uint32_t flags = iceberg_build_range<B, B2, W, COUNT>(g, wave_range(g.n), &probes);
   if (flags) atomicOr(g.status, flags);
   if (COUNT) {
     const uint32_t total = wave_sum(probes);

@@ -243,3 +243,77 @@ def test_load_balanced_cuckoo_reaches_loads_power_of_two_cannot():
     assert st == B.BHT_OK
     assert oracle.check32(p, t.download(), keys, vals)[0] == 0
     t.close()
+
+
+ICEBERG_PARTITIONED = [
+    # b, b2, threshold, lf, n
+    (16, 0, 12, 0.8, 1 << 18),
+    (16, 0, 9, 0.86, 100003),
+    (32, 0, 25, 0.9, 1 << 18),
+    (16, 8, 16, 0.8, 1 << 18),
+    (16, 8, 16, 0.86, 300007),
+    (32, 8, 32, 0.85, 1 << 17),
+    (16, 8, 16, 0.86, 1 << 23),          # 1,059 bins: two radix passes
+    (16, 0, 4, 0.5, 5000),               # low threshold, a single bin
+    (16, 8, 16, 0.8, 3),
+]
+
+
+@pytest.mark.parametrize("b,b2,thr,lf,n", ICEBERG_PARTITIONED)
+def test_iceberg_partitioned_build(b, b2, thr, lf, n):
+    """Partitioned iceberg build (primaries filled on chip up to t pairs, the
+    rest inserted at their secondary choices): the oracle's invariant checker
+    (including: every secondary key's primary holds at least t keys), exact
+    lookups and per-query probes, and the number of pairs sent on from the
+    primaries equals the primary overflow sum max(0, X_j - t)."""
+    B = bht()
+    print("iceberg partitioned b=%d b2=%d t=%d lf=%g n=%d" % (b, b2, thr, lf, n), flush=True)
+    keys, vals = workload(n, 41)
+    for s in range(12):
+        p = iceberg_params(n, lf, 4100 + s, b=b, b2=b2, threshold=thr)
+        t = B.Table(p.m * p.b, p.b, p.scheme, p.a, p.c, rng_seed=p.rng_seed,
+                    max_chain=p.max_chain, iht_threshold=p.threshold, iht_secondary_b=p.b2,
+                    iht_secondary_m=p.m2, build_mode="partitioned")
+        st = t.build(dev(keys), dev(vals))
+        if st == B.BHT_OK:
+            break
+        assert st == B.BHT_ERR_BUILD_FAILED
+        t.close()
+    assert st == B.BHT_OK
+    code, msg = oracle.check32(p, t.download(), keys, vals)
+    assert code == 0, msg
+    part, sent_on, _ = B.bht_build_stats(t.handle)
+    h0 = oracle.hash32_many(p.a[0], p.c[0], keys, p.m)
+    counts = np.bincount(h0.astype(np.int64), minlength=p.m)
+    assert part and sent_on == int(np.maximum(counts - min(thr, b), 0).sum())
+    nq = min(n, 1 << 20)
+    for frac in (1.0, 0.0):
+        check_find(t, p, keys, vals, datagen.mixed_queries(n, nq, frac, 41))
+    t.close()
+
+
+def test_iceberg_build_modes_agree():
+    """Concurrent and partitioned iceberg builds of the same input give valid
+    layouts and identical lookups; below 2^26 pairs the default takes the
+    concurrent path."""
+    import torch
+    B = bht()
+    n = 1 << 19
+    keys, vals = workload(n, 42)
+    p = iceberg_params(n, 0.8, 4200, b=16, b2=8, threshold=16)
+    q = datagen.mixed_queries(n, n, 0.5, 42)
+    results = []
+    for mode in ("concurrent", "auto", "partitioned"):
+        t = B.Table(p.m * p.b, p.b, p.scheme, p.a, p.c, rng_seed=p.rng_seed,
+                    iht_threshold=p.threshold, iht_secondary_b=p.b2, iht_secondary_m=p.m2,
+                    build_mode=mode)
+        assert t.build(dev(keys), dev(vals)) == B.BHT_OK
+        assert oracle.check32(p, t.download(), keys, vals)[0] == 0
+        assert B.bht_build_stats(t.handle)[0] == (mode == "partitioned")
+        v, f = t.find(dev(q))
+        torch.cuda.synchronize()
+        results.append((host_u32(v), host_u8(f)))
+        t.close()
+    for v, f in results[1:]:
+        np.testing.assert_array_equal(v, results[0][0])
+        np.testing.assert_array_equal(f, results[0][1])
