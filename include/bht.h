@@ -166,10 +166,11 @@ bht_status bht_build_retry(bht_table* t, const void* d_keys, const void* d_value
 /* Statistics of the last successful build: *partitioned = 1 if it
  * took the partitioned path (see bht_tuning), else 0.  For a partitioned
  * build, *evicted = pairs that met a full first bucket and evicted a
- * resident on chip, and *overflow_probes = bucket reads made while those
- * evicted pairs were inserted (Section VII-E's probe: one bucket read);
- * both 0 for a concurrent build.  Returns NOT_BUILT before a successful
- * build. */
+ * resident on chip (iceberg tables: pairs that met a primary holding t
+ * pairs and went on to the secondary step), and *overflow_probes = bucket
+ * reads made while those pairs were inserted (Section VII-E's probe: one
+ * bucket read); both 0 for a concurrent build.  Returns NOT_BUILT before a
+ * successful build. */
 bht_status bht_build_stats(const bht_table* t, uint32_t* partitioned, uint64_t* evicted,
                            uint64_t* overflow_probes);
 
