@@ -376,14 +376,22 @@ def run_schemes(args):
                 probes[qname.replace("find_", "")] = float(pr.sum(dtype=torch.int64).item()) / n
             entry["probes_per_key"] = {k: None if v is None else round(v, 4) for k, v in probes.items()}
             entry["accesses_gps"] = {}
+        else:
+            # query probe averages from the instrumented 64-bit find (untimed)
+            pr = torch.empty(n, dtype=torch.uint8, device=dev)
+            probes = {"insert": None}
+            for qname in ("find_pos", "find_neg", "find_mix"):
+                bht.bht_find64_counted(table.handle, d_q[qname], out_v, out_f, pr, stream=stream)
+                probes[qname.replace("find_", "")] = float(pr.sum(dtype=torch.int64).item()) / n
+            entry["probes_per_key"] = {k: None if v is None else round(v, 4) for k, v in probes.items()}
+            entry["accesses_gps"] = {}
         for k, v in ms.items():
             avg = float(np.mean(v))
             entry[k + "_ms"] = round(avg, 4)
             entry[k + "_gkeys_s"] = round(n / (avg * 1e-3) / 1e9, 4)
-            if not wide:
-                p = entry["probes_per_key"]["insert" if k == "build" else k.replace("find_", "")]
-                if p is not None:
-                    entry["accesses_gps"][k] = round(p * n / (avg * 1e-3) / 1e9, 2)
+            p = entry["probes_per_key"]["insert" if k == "build" else k.replace("find_", "")]
+            if p is not None:
+                entry["accesses_gps"][k] = round(p * n / (avg * 1e-3) / 1e9, 2)
         if scheme == "iht":
             # the early-exit find (a miss in a primary below t ends the query)
             bht.bht_set_tuning(table.handle, iht_early_exit=True)

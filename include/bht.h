@@ -222,6 +222,11 @@ bht_status bht_build_counted(bht_table* t, const uint32_t* d_keys, const uint32_
 bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint64_t n,
                             uint32_t* d_out_values, uint8_t* d_out_found, uint8_t* d_probes,
                             void* stream);
+/* bht_find64 that also writes each query's bucket reads to d_probes[i]
+ * (device uint8).  INVALID_ARG for a null probe array. */
+bht_status bht_find64_counted(const bht_table* t, const uint64_t* d_queries, uint64_t n,
+                              uint64_t* d_out_values, uint8_t* d_out_found, uint8_t* d_probes,
+                              void* stream);
 
 /* Tuning (speed only, never results).  tile_width: lanes that read one
  * bucket together (1 for bucket_size 1; 4, 8 or 16 otherwise, at most

@@ -84,7 +84,7 @@ def lib():
         _lib.orc_insert32.restype = ctypes.c_int
         _lib.orc_insert32.argtypes = [p, p, u32, u32, p, p]
         _lib.orc_find32.argtypes = [p, p, p, u64, p, p, p, p]
-        _lib.orc_find64.argtypes = [p, p, p, u64, p, p, p]
+        _lib.orc_find64.argtypes = [p, p, p, u64, p, p, p, p]
         _lib.orc_brute_find32.argtypes = [p, p, u64, p, u64, p, p]
         _lib.orc_brute_find64.argtypes = [p, p, u64, p, u64, p, p]
         for name in ("orc_check32", "orc_check64"):
@@ -246,15 +246,17 @@ def build64(params: Params, keys: np.ndarray, vals: np.ndarray):
 
 
 def find64(params: Params, table: np.ndarray, queries: np.ndarray):
+    """Serial find.  Returns (values, found, total probes, per-query probes)."""
     q = np.ascontiguousarray(queries, dtype=np.uint64)
     table = np.ascontiguousarray(table, dtype=np.uint64)
     pc = params.to_c()
     out_v = np.empty(len(q), dtype=np.uint64)
     out_f = np.empty(len(q), dtype=np.uint8)
+    per = np.empty(len(q), dtype=np.uint8)
     probes = ctypes.c_uint64(0)
     lib().orc_find64(ctypes.byref(pc), _ptr(table), _ptr(q), len(q), _ptr(out_v), _ptr(out_f),
-                     ctypes.byref(probes))
-    return out_v, out_f, probes.value
+                     ctypes.byref(probes), _ptr(per))
+    return out_v, out_f, probes.value, per
 
 
 def brute_find64(keys: np.ndarray, vals: np.ndarray, queries: np.ndarray):

@@ -397,15 +397,16 @@ void orc_find32(const orc_params* p, const uint64_t* table, const uint32_t* q,
 }
 
 void orc_find64(const orc_params* p, const uint64_t* table, const uint64_t* q,
-                uint64_t nq, uint64_t* out_v, uint8_t* out_f, uint64_t* probes) {
+                uint64_t nq, uint64_t* out_v, uint8_t* out_f, uint64_t* probes,
+                uint8_t* per_query_probes) {
   uint64_t total = 0;
   for (uint64_t i = 0; i < nq; i++) {
     uint64_t v = EMPTY64;
-    uint8_t found = 0;
+    uint8_t found = 0, pr = 0;
     if (q[i] != EMPTY64) {
       for (uint32_t j = 0; j < p->h; j++) {
         bucket_ref B = bucket64(p, j, q[i]);
-        total++;
+        pr++;
         for (uint32_t s = 0; s < B.size; s++) {
           if (table[2 * (B.first_slot + s)] == q[i]) {
             v = table[2 * (B.first_slot + s) + 1];
@@ -418,6 +419,8 @@ void orc_find64(const orc_params* p, const uint64_t* table, const uint64_t* q,
     }
     out_v[i] = found ? v : EMPTY64;
     out_f[i] = found;
+    if (per_query_probes) per_query_probes[i] = pr;
+    total += pr;
   }
   if (probes) *probes = total;
 }

@@ -82,7 +82,8 @@ void orc_find32(const orc_params* p, const uint64_t* table, const uint32_t* q,
                 uint64_t nq, uint32_t* out_v, uint8_t* out_f, uint64_t* probes,
                 uint8_t* per_query_probes);
 void orc_find64(const orc_params* p, const uint64_t* table, const uint64_t* q,
-                uint64_t nq, uint64_t* out_v, uint8_t* out_f, uint64_t* probes);
+                uint64_t nq, uint64_t* out_v, uint8_t* out_f, uint64_t* probes,
+                uint8_t* per_query_probes);
 
 /* Plain definition of a lookup over the input pairs: sort + binary search. */
 void orc_brute_find32(const uint32_t* keys, const uint32_t* vals, uint64_t n,

@@ -96,6 +96,7 @@ _SIGS = {
     "bht_params_from_seed": (_st, [_u64, ctypes.c_int, _u32, ctypes.POINTER(bht_params)]),
     "bht_build_retry": (_st, [_p, _p, _p, _u64, _u64, _u32, ctypes.POINTER(_u32), _p]),
     "bht_find_counted": (_st, [_p, _p, _u64, _p, _p, _p, _p]),
+    "bht_find64_counted": (_st, [_p, _p, _u64, _p, _p, _p, _p]),
     "bht_set_tuning": (_st, [_p, ctypes.POINTER(bht_tuning)]),
     "bht_get_tuning": (_st, [_p, ctypes.POINTER(bht_tuning)]),
     "bht_enable_timing": (_st, [_p, ctypes.c_int]),
@@ -315,6 +316,15 @@ def bht_find_counted(table, queries, out_values, out_found, probes, n=None, stre
                                  _dptr(out_found, None, "out_found"),
                                  _dptr(probes, None, "probes"), _stream(stream)),
            "bht_find_counted")
+
+
+def bht_find64_counted(table, queries, out_values, out_found, probes, n=None, stream=None):
+    n = queries.numel() if n is None else n
+    _check(_lib.bht_find64_counted(table, _dptr(queries, None, "queries"), n,
+                                   _dptr(out_values, None, "out_values"),
+                                   _dptr(out_found, None, "out_found"),
+                                   _dptr(probes, None, "probes"), _stream(stream)),
+           "bht_find64_counted")
 
 
 def bht_set_tuning(table, tile_width: int = 0, find_schedule=0, grid_blocks: int = 0,

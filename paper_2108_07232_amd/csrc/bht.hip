@@ -1159,30 +1159,52 @@ bht_status bht_build64(bht_table* t, const uint64_t* d_keys, const uint64_t* d_v
   return bht_build_wait(t, stream);
 }
 
-bht_status bht_find64(const bht_table* t, const uint64_t* d_queries, uint64_t n,
-                      uint64_t* d_out_values, uint8_t* d_out_found, void* stream) {
+}  // extern "C"
+
+namespace {
+
+bht_status find64_enqueue(const bht_table* t, const uint64_t* q, uint64_t n, uint64_t* out_v,
+                          uint8_t* out_f, uint8_t* probes, void* stream) {
   if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
   if (t->key_bits != 64) return fail(BHT_ERR_INVALID_ARG, "table holds 32-bit keys");
   if (!t->built) return fail(BHT_ERR_NOT_BUILT, "find before a successful build");
   if (n == 0) return BHT_OK;
-  if (!d_queries || !d_out_values || !d_out_found)
-    return fail(BHT_ERR_INVALID_ARG, "null query or output pointer");
+  if (!q || !out_v || !out_f) return fail(BHT_ERR_INVALID_ARG, "null query or output pointer");
   WideFindArgs g;
   g.slots = t->d_slots;
-  g.queries = d_queries;
+  g.queries = q;
   g.n = n;
-  g.out_v = d_out_values;
-  g.out_f = d_out_found;
+  g.out_v = out_v;
+  g.out_f = out_f;
+  g.probes = probes;
   g.H = make_hash64(t->params, t->m, t->params.num_hashes);
   hipStream_t st = as_stream(stream);
-  const int grid = grid_for((const void*)wide_find_chunk_kernel<8>, n, t->grid_blocks, 16);
+  const void* kernel = probes ? (const void*)wide_find_chunk_kernel<8, true>
+                              : (const void*)wide_find_chunk_kernel<8, false>;
+  const int grid = grid_for(kernel, n, t->grid_blocks, 16);
   bht_table* mt = const_cast<bht_table*>(t);
   if (t->timing) HIP_TRY(hipEventRecord(t->ev[2], st));
-  wide_find_chunk_kernel<8><<<grid, kBlock, 0, st>>>(g);
+  reinterpret_cast<void (*)(WideFindArgs)>(const_cast<void*>(kernel)) <<<grid, kBlock, 0, st>>>(g);
   HIP_TRY(hipGetLastError());
   if (t->timing) HIP_TRY(hipEventRecord(t->ev[3], st));
   mt->find_timed = t->timing;
   return BHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bht_status bht_find64(const bht_table* t, const uint64_t* d_queries, uint64_t n,
+                      uint64_t* d_out_values, uint8_t* d_out_found, void* stream) {
+  return find64_enqueue(t, d_queries, n, d_out_values, d_out_found, nullptr, stream);
+}
+
+bht_status bht_find64_counted(const bht_table* t, const uint64_t* d_queries, uint64_t n,
+                              uint64_t* d_out_values, uint8_t* d_out_found, uint8_t* d_probes,
+                              void* stream) {
+  if (!d_probes) return fail(BHT_ERR_INVALID_ARG, "null probe array");
+  return find64_enqueue(t, d_queries, n, d_out_values, d_out_found, d_probes, stream);
 }
 
 bht_status bht_set_tuning(bht_table* t, const bht_tuning* tuning) {

@@ -108,6 +108,7 @@ struct WideFindArgs {
   uint64_t n;
   uint64_t* out_v;
   uint8_t* out_f;
+  uint8_t* probes;             // per-query bucket reads (COUNT kernels)
   Hash64 H;
 };
 
@@ -288,8 +289,8 @@ __device__ __forceinline__ uint64_t group_any(uint64_t x) {
 // is closed is not loaded; the tile reductions of the ballots are scalar
 // (bit t*W + j of hacc / eacc is tile t's answer for its lane j); the one
 // matching lane of a tile (keys are unique) leaves the value in the owner's
-// LDS word.
-template <int W>
+// LDS word.  COUNT: each query's bucket reads go to g.probes.
+template <int W, bool COUNT = false>
 __global__ __launch_bounds__(kBlock) void wide_find_chunk_kernel(WideFindArgs g) {
   constexpr int B = W;
   const uint32_t lane = __lane_id();
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void wide_find_chunk_kernel(WideFindArgs g)
     q_next = (base + 64 + lane < r.end) ? g.queries[base + 64 + lane] : kEmpty64;
     bool open = valid && q < kBusy64;
     uint64_t out = kEmpty64;
-    uint8_t found = 0;
+    uint8_t found = 0, rounds = 0;
     uint64_t qt[W];
 #pragma unroll
     for (int j = 0; j < W; ++j) qt[j] = shfl64(q, tb + j);
@@ -335,6 +336,7 @@ __global__ __launch_bounds__(kBlock) void wide_find_chunk_kernel(WideFindArgs g)
         eacc |= group_any<W>(__builtin_amdgcn_ballot_w64(d[j].x == kEmpty64)) << j;
       }
       if (open) {
+        rounds = (uint8_t)(round + 1);
         if ((hacc >> lane) & 1ull) {
           out = vbuf[lane];
           found = 1;
@@ -347,6 +349,7 @@ __global__ __launch_bounds__(kBlock) void wide_find_chunk_kernel(WideFindArgs g)
     if (valid) {
       g.out_v[idx] = out;
       g.out_f[idx] = found;
+      if (COUNT) g.probes[idx] = rounds;
     }
   }
 }

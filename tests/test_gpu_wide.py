@@ -191,3 +191,30 @@ def test_wide_partitioned_crowded_bucket_and_status_paths():
     t = bht.Table(p.m * 8, 8, "bcht", same[0], same[1], key_bits=64, build_mode="partitioned")
     assert t.build(dev(keys), dev(vals)) == bht.BHT_ERR_BUILD_FAILED
     t.close()
+
+
+@pytest.mark.parametrize("n,lf,mode", [(1 << 20, 0.9, "partitioned"), (50001, 0.95, "concurrent"),
+                                       (3000, 0.9, "partitioned")])
+def test_wide_counted_find_probes_equal_oracle(n, lf, mode):
+    """Per-query bucket reads of the counted 64-bit find equal the oracle's
+    find replayed on the GPU's own layout (Section VII-E's probe); results
+    equal brute force."""
+    import torch
+    import paper_2108_07232_amd as bht
+    t, p, keys, vals = build_mode64(n, lf, 11, mode)
+    layout = t.download()
+    for frac in (1.0, 0.5, 0.0):
+        q = datagen.mixed_queries(n, n, frac, 11, wide=True)
+        out_v = torch.empty(n, dtype=torch.int64, device="cuda")
+        out_f = torch.empty(n, dtype=torch.uint8, device="cuda")
+        pr = torch.empty(n, dtype=torch.uint8, device="cuda")
+        bht.bht_find64_counted(t.handle, dev(q), out_v, out_f, pr)
+        torch.cuda.synchronize()
+        bv, bf = oracle.brute_find64(keys, vals, q)
+        np.testing.assert_array_equal(host_u8(out_f), bf)
+        np.testing.assert_array_equal(host_u64(out_v), bv)
+        _, _, _, per = oracle.find64(p, layout, q)
+        np.testing.assert_array_equal(host_u8(pr), per)
+    with pytest.raises(bht.BhtError):
+        bht.bht_find64_counted(t.handle, dev(q), out_v, out_f, None)
+    t.close()

@@ -276,7 +276,8 @@ def test_oracle_64bit_find_equals_brute_force():
         assert st == oracle.OK
         assert oracle.check64(params, table, keys, vals) == (0, "ok")
         q = datagen.mixed_queries(n, 2 * n, 0.5, seed, wide=True)
-        v, f, _ = oracle.find64(params, table, q)
+        v, f, total, per = oracle.find64(params, table, q)
+        assert int(per.sum(dtype=np.int64)) == total
         bv, bf = oracle.brute_find64(keys, vals, q)
         np.testing.assert_array_equal(f, bf)
         np.testing.assert_array_equal(v, bv)
