@@ -1,5 +1,6 @@
 // Partitioned bulk build of a bucketed cuckoo table (BCHT, and the
-// one-slot table).
+// one-slot table); the radix passes and the placement without eviction
+// also serve the iceberg table's build.
 //
 // The paper's build inserts every pair concurrently with one bucket read
 // and one slot atomic each (Section V-B).  On MI355X the slot atomics are
@@ -38,7 +39,7 @@
 namespace bht {
 
 // Threads per counting / scatter block and pairs staged per sub-tile
-// (compile-time tuning; the sub-tile is 8 pairs per thread).
+// (compile-time tuning; by default 16 pairs per thread).
 #ifndef BHT_PASS_BLOCK
 #define BHT_PASS_BLOCK 1024
 #endif
@@ -51,8 +52,7 @@ namespace bht {
 constexpr int kScatterBlocksPerCU = BHT_SCATTER_BLOCKS_PER_CU;   // occupancy the scatter is compiled for
 constexpr int kPartBlock = 256;                        // threads per scan block
 constexpr int kPassBlock = BHT_PASS_BLOCK;
-constexpr int kPartSub = BHT_PASS_PER * kPassBlock;
-constexpr int kPartPer = kPartSub / kPassBlock;        // pairs per thread per sub-tile
+constexpr int kPartSub = BHT_PASS_PER * kPassBlock;   // pairs per sub-tile (4-byte words)
 constexpr uint32_t kPartChunkMax = 4 * kPartSub;       // pairs per partition block, at most
 constexpr uint32_t kMaxFan = 1024;                     // digits of the first pass, at most
 constexpr uint32_t kFan2 = 256;                        // digits of the second pass
@@ -107,7 +107,6 @@ struct PartPassT {
   PartPlan P;
   PartMeta M;
 };
-using PartPass = PartPassT<uint32_t>;
 using PartPass64 = PartPassT<uint64_t>;
 
 __device__ __forceinline__ uint32_t part_split(const PartPlan& P, uint32_t level, uint32_t bin) {
