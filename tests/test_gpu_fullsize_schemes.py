@@ -1,0 +1,87 @@
+"""Parity at the scheme comparison's full size (2^27 keys) for the two
+tables whose default build at that size is a partitioned one: the 64-bit
+BCHT (8 16-byte slots per bucket, LF 0.9) and the two-level iceberg table
+(16-slot primaries, 8-slot secondaries of 1/8 the primary slots, t = 16,
+LF 0.85), built and queried as the benchmark does.
+
+The whole GPU layout goes through the oracle's invariant checker; every
+query is checked against properties that hold at any size (all positives
+found, no negative found, a half-positive batch finds exactly half); a
+sample of each batch is checked value for value against brute force."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests._util import dev, host_u32, host_u64, host_u8
+from tests.test_gpu_schemes import iceberg_params
+
+pytestmark = pytest.mark.gpu
+
+N = 1 << 27
+SAMPLE = 1 << 20
+
+
+def check_batches(t, keys, vals, wide, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    samples = []
+    for frac in (1.0, 0.0, 0.5):
+        q = datagen.mixed_queries(N, N, frac, seed, wide=wide)
+        v, f = t.find(dev(q))
+        torch.cuda.synchronize()
+        hf = host_u8(f)
+        assert int(hf.sum()) == int(frac * N), frac
+        idx = rng.choice(N, SAMPLE, replace=False)
+        hv = host_u64(v) if wide else host_u32(v)
+        samples.append((q[idx], hv[idx], hf[idx]))
+        del v, f
+        print("  batch %.1f positive checked" % frac, flush=True)
+    q = np.concatenate([s[0] for s in samples])
+    brute = oracle.brute_find64 if wide else oracle.brute_find32
+    ev, ef = brute(keys, vals, q)
+    np.testing.assert_array_equal(np.concatenate([s[2] for s in samples]), ef)
+    np.testing.assert_array_equal(np.concatenate([s[1] for s in samples]), ev)
+
+
+def test_full_size_64bit():
+    import paper_2108_07232_amd as bht
+    print("full-size parity: 64-bit BCHT, 2^27 keys, LF 0.9", flush=True)
+    keys, vals = datagen.unique_keys64(N, 1), datagen.values64(N, 1)
+    for s in range(4):
+        p = oracle.params_for("bcht", N, 0.9, 1 + s, b=8, wide=True)
+        t = bht.Table(p.m * 8, 8, "bcht", p.a, p.c, key_bits=64, rng_seed=p.rng_seed)
+        st = t.build(dev(keys), dev(vals))
+        if st == bht.BHT_OK:
+            break
+        assert st == bht.BHT_ERR_BUILD_FAILED
+        t.close()
+    assert st == bht.BHT_OK
+    assert bht.bht_build_stats(t.handle)[0]            # the partitioned path
+    code, msg = oracle.check64(p, t.download(), keys, vals)
+    assert code == 0, msg
+    print("  layout checked", flush=True)
+    check_batches(t, keys, vals, True, 1)
+    t.close()
+
+
+def test_full_size_iceberg_two_level():
+    import paper_2108_07232_amd as bht
+    print("full-size parity: two-level iceberg, 2^27 keys, LF 0.85", flush=True)
+    keys, vals = datagen.unique_keys(N, 2), datagen.values(N, 2)
+    for s in range(4):
+        p = iceberg_params(N, 0.85, 20 + s, b=16, b2=8, threshold=16)
+        t = bht.Table(p.m * p.b, p.b, p.scheme, p.a, p.c, rng_seed=p.rng_seed,
+                      iht_threshold=p.threshold, iht_secondary_b=p.b2, iht_secondary_m=p.m2)
+        st = t.build(dev(keys), dev(vals))
+        if st == bht.BHT_OK:
+            break
+        assert st == bht.BHT_ERR_BUILD_FAILED
+        t.close()
+    assert st == bht.BHT_OK
+    assert bht.bht_build_stats(t.handle)[0]            # the partitioned path
+    code, msg = oracle.check32(p, t.download(), keys, vals)
+    assert code == 0, msg
+    print("  layout checked", flush=True)
+    check_batches(t, keys, vals, False, 2)
+    t.close()
