@@ -1,8 +1,9 @@
-"""Parity at the scheme comparison's full size (2^27 keys) for the two
-tables whose default build at that size is a partitioned one: the 64-bit
-BCHT (8 16-byte slots per bucket, LF 0.9) and the two-level iceberg table
-(16-slot primaries, 8-slot secondaries of 1/8 the primary slots, t = 16,
-LF 0.85), built and queried as the benchmark does.
+"""Parity at the scheme comparison's full size (2^27 keys) for the tables
+whose default build at that size is a partitioned one besides the 2^28
+BCHT: the 64-bit BCHT (8 16-byte slots per bucket, LF 0.9), the two-level
+iceberg table (16-slot primaries, 8-slot secondaries of 1/8 the primary
+slots, t = 16, LF 0.85) and the one-slot cuckoo table (h = 3, LF 0.8),
+built and queried as the benchmark does.
 
 The whole GPU layout goes through the oracle's invariant checker; every
 query is checked against properties that hold at any size (all positives
@@ -84,4 +85,25 @@ def test_full_size_iceberg_two_level():
     assert code == 0, msg
     print("  layout checked", flush=True)
     check_batches(t, keys, vals, False, 2)
+    t.close()
+
+
+def test_full_size_one_slot_cuckoo():
+    import paper_2108_07232_amd as bht
+    print("full-size parity: 1CHT (b = 1, h = 3), 2^27 keys, LF 0.8", flush=True)
+    keys, vals = datagen.unique_keys(N, 3), datagen.values(N, 3)
+    for s in range(4):
+        p = oracle.params_for("cht1", N, 0.8, 30 + s, b=1)
+        t = bht.Table(p.m, 1, "cht1", p.a, p.c, rng_seed=p.rng_seed)
+        st = t.build(dev(keys), dev(vals))
+        if st == bht.BHT_OK:
+            break
+        assert st == bht.BHT_ERR_BUILD_FAILED
+        t.close()
+    assert st == bht.BHT_OK
+    assert bht.bht_build_stats(t.handle)[0]            # the partitioned path
+    code, msg = oracle.check32(p, t.download(), keys, vals)
+    assert code == 0, msg
+    print("  layout checked", flush=True)
+    check_batches(t, keys, vals, False, 3)
     t.close()
