@@ -87,6 +87,8 @@ def lib():
         _lib.orc_find64.argtypes = [p, p, p, u64, p, p, p, p]
         _lib.orc_brute_find32.argtypes = [p, p, u64, p, u64, p, p]
         _lib.orc_brute_find64.argtypes = [p, p, u64, p, u64, p, p]
+        _lib.orc_join_find32.argtypes = [p, p, u64, p, u64, p, p]
+        _lib.orc_join_find64.argtypes = [p, p, u64, p, u64, p, p]
         for name in ("orc_check32", "orc_check64"):
             getattr(_lib, name).restype = ctypes.c_int
             getattr(_lib, name).argtypes = [p, p, p, p, u64, ctypes.c_char_p, ctypes.c_int]
@@ -222,6 +224,20 @@ def brute_find32(keys: np.ndarray, vals: np.ndarray, queries: np.ndarray):
     return out_v, out_f
 
 
+def join_find32(keys: np.ndarray, vals: np.ndarray, queries: np.ndarray):
+    """brute_find32's results by a sort-merge join (linear time: every query
+    of a 2^28-query batch in seconds)."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint32)
+    vals = np.ascontiguousarray(vals, dtype=np.uint32)
+    q = np.ascontiguousarray(queries, dtype=np.uint32)
+    assert len(q) < (1 << 32)
+    out_v = np.empty(len(q), dtype=np.uint32)
+    out_f = np.empty(len(q), dtype=np.uint8)
+    lib().orc_join_find32(_ptr(keys), _ptr(vals), len(keys), _ptr(q), len(q), _ptr(out_v),
+                          _ptr(out_f))
+    return out_v, out_f
+
+
 def check32(params: Params, table: np.ndarray, keys: np.ndarray, vals: np.ndarray):
     """Layout invariants.  Returns (0, 'ok') or (invariant number, message)."""
     keys = np.ascontiguousarray(keys, dtype=np.uint32)
@@ -267,6 +283,18 @@ def brute_find64(keys: np.ndarray, vals: np.ndarray, queries: np.ndarray):
     out_f = np.empty(len(q), dtype=np.uint8)
     lib().orc_brute_find64(_ptr(keys), _ptr(vals), len(keys), _ptr(q), len(q), _ptr(out_v),
                            _ptr(out_f))
+    return out_v, out_f
+
+
+def join_find64(keys: np.ndarray, vals: np.ndarray, queries: np.ndarray):
+    """brute_find64's results by a sort-merge join (linear time)."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    vals = np.ascontiguousarray(vals, dtype=np.uint64)
+    q = np.ascontiguousarray(queries, dtype=np.uint64)
+    out_v = np.empty(len(q), dtype=np.uint64)
+    out_f = np.empty(len(q), dtype=np.uint8)
+    lib().orc_join_find64(_ptr(keys), _ptr(vals), len(keys), _ptr(q), len(q), _ptr(out_v),
+                          _ptr(out_f))
     return out_v, out_f
 
 

@@ -514,6 +514,117 @@ void orc_brute_find64(const uint64_t* keys, const uint64_t* vals, uint64_t n,
   free(s);
 }
 
+/* Stable ascending sort of n uint64 values by bits [lo, 64):
+ * least-significant-digit radix sort over 11-bit digits. */
+static void sort_u64_from_bit(uint64_t* a, uint64_t n, int lo) {
+  if (n < 2) return;
+  uint64_t* tmp = (uint64_t*)malloc(n * sizeof(uint64_t));
+  uint64_t count[2048];
+  uint64_t *src = a, *dst = tmp;
+  for (int shift = lo; shift < 64; shift += 11) {
+    memset(count, 0, sizeof(count));
+    for (uint64_t i = 0; i < n; i++) count[(src[i] >> shift) & 2047]++;
+    uint64_t sum = 0;
+    for (int d = 0; d < 2048; d++) {
+      uint64_t c = count[d];
+      count[d] = sum;
+      sum += c;
+    }
+    for (uint64_t i = 0; i < n; i++) dst[count[(src[i] >> shift) & 2047]++] = src[i];
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != a) memcpy(a, src, n * sizeof(uint64_t));
+  free(tmp);
+}
+
+/* Stable ascending sort of n (key, value) records by key: least-significant-
+ * digit radix sort over 11-bit digits of the key. */
+static void sort_kv64(kv64* a, uint64_t n) {
+  if (n < 2) return;
+  kv64* tmp = (kv64*)malloc(n * sizeof(kv64));
+  uint64_t count[2048];
+  kv64 *src = a, *dst = tmp;
+  for (int shift = 0; shift < 64; shift += 11) {
+    memset(count, 0, sizeof(count));
+    for (uint64_t i = 0; i < n; i++) count[(src[i].k >> shift) & 2047]++;
+    uint64_t sum = 0;
+    for (int d = 0; d < 2048; d++) {
+      uint64_t c = count[d];
+      count[d] = sum;
+      sum += c;
+    }
+    for (uint64_t i = 0; i < n; i++) dst[count[(src[i].k >> shift) & 2047]++] = src[i];
+    kv64* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != a) memcpy(a, src, n * sizeof(kv64));
+  free(tmp);
+}
+
+/* The lookup of orc_brute_find32 computed as a sort-merge join: the pairs
+ * sorted by key, the queries sorted by value together with their positions,
+ * one merge pass matching equal keys, each answer written back to its
+ * query's position.  Same results; linear time, so that every query of a
+ * 2^28-query batch can be checked.  nq must be below 2^32. */
+void orc_join_find32(const uint32_t* keys, const uint32_t* vals, uint64_t n,
+                     const uint32_t* q, uint64_t nq, uint32_t* out_v, uint8_t* out_f) {
+  uint64_t* s = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+  uint64_t* qs = (uint64_t*)malloc((nq ? nq : 1) * sizeof(uint64_t));
+  for (uint64_t i = 0; i < n; i++) s[i] = ((uint64_t)keys[i] << 32) | vals[i];
+  for (uint64_t i = 0; i < nq; i++) qs[i] = ((uint64_t)q[i] << 32) | i;
+  sort_u64_from_bit(s, n, 32);       /* by key */
+  sort_u64_from_bit(qs, nq, 32);     /* by query */
+  uint64_t j = 0;
+  for (uint64_t r = 0; r < nq; r++) {
+    const uint32_t qv = (uint32_t)(qs[r] >> 32);
+    const uint64_t i = (uint32_t)qs[r];
+    while (j < n && (uint32_t)(s[j] >> 32) < qv) j++;
+    if (j < n && (uint32_t)(s[j] >> 32) == qv && qv != EMPTY32) {
+      out_v[i] = (uint32_t)s[j];
+      out_f[i] = 1;
+    } else {
+      out_v[i] = EMPTY32;
+      out_f[i] = 0;
+    }
+  }
+  free(s);
+  free(qs);
+}
+
+/* orc_brute_find64 as a sort-merge join (see orc_join_find32). */
+void orc_join_find64(const uint64_t* keys, const uint64_t* vals, uint64_t n,
+                     const uint64_t* q, uint64_t nq, uint64_t* out_v, uint8_t* out_f) {
+  kv64* s = (kv64*)malloc((n ? n : 1) * sizeof(kv64));
+  kv64* qs = (kv64*)malloc((nq ? nq : 1) * sizeof(kv64));
+  for (uint64_t i = 0; i < n; i++) {
+    s[i].k = keys[i];
+    s[i].v = vals[i];
+  }
+  for (uint64_t i = 0; i < nq; i++) {
+    qs[i].k = q[i];
+    qs[i].v = i;
+  }
+  sort_kv64(s, n);
+  sort_kv64(qs, nq);
+  uint64_t j = 0;
+  for (uint64_t r = 0; r < nq; r++) {
+    const uint64_t qv = qs[r].k, i = qs[r].v;
+    while (j < n && s[j].k < qv) j++;
+    if (j < n && s[j].k == qv && qv != EMPTY64) {
+      out_v[i] = s[j].v;
+      out_f[i] = 1;
+    } else {
+      out_v[i] = EMPTY64;
+      out_f[i] = 0;
+    }
+  }
+  free(s);
+  free(qs);
+}
+
 /* ------------------------------------------------------------ invariants */
 
 /*

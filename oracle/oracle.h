@@ -91,6 +91,13 @@ void orc_brute_find32(const uint32_t* keys, const uint32_t* vals, uint64_t n,
 void orc_brute_find64(const uint64_t* keys, const uint64_t* vals, uint64_t n,
                       const uint64_t* q, uint64_t nq, uint64_t* out_v, uint8_t* out_f);
 
+/* The same lookups as a sort-merge join (linear time; nq < 2^32), for
+ * checking every query of full-size batches. */
+void orc_join_find32(const uint32_t* keys, const uint32_t* vals, uint64_t n,
+                     const uint32_t* q, uint64_t nq, uint32_t* out_v, uint8_t* out_f);
+void orc_join_find64(const uint64_t* keys, const uint64_t* vals, uint64_t n,
+                     const uint64_t* q, uint64_t nq, uint64_t* out_v, uint8_t* out_f);
+
 /* Layout invariants I1..I6 (see orc_check32 in oracle.c).  Returns 0 when
  * all hold, else the number of the first violated invariant, with a message
  * in msg. */

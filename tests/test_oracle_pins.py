@@ -211,6 +211,46 @@ def test_brute_force64_matches_dictionary():
         assert (fi == 1 and vi == d[qi]) if qi in d else (fi == 0 and vi == (1 << 64) - 1)
 
 
+def test_join_lookup_matches_dictionary():
+    """The sort-merge join used for full-size checks answers like a Python
+    dictionary: keys spanning all 32 bits (every radix digit), repeated
+    queries, the reserved key, empty inputs."""
+    rng = np.random.default_rng(9)
+    for n, nq in [(0, 10), (1, 0), (1, 5), (7, 100), (5000, 20000), (100000, 300000)]:
+        keys = np.unique(rng.integers(0, 0xFFFFFFFF, size=2 * n + 4, dtype=np.uint64))
+        keys = rng.permutation(keys)[:n].astype(np.uint32)
+        vals = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+        pool = np.concatenate([keys, rng.integers(0, 1 << 32, size=max(n, 8),
+                                                   dtype=np.uint64).astype(np.uint32),
+                               np.array([0xFFFFFFFF, 0], dtype=np.uint32)])
+        q = pool[rng.integers(0, len(pool), size=nq)]
+        d = dict(zip(keys.tolist(), vals.tolist()))
+        v, f = oracle.join_find32(keys, vals, q)
+        ev = np.array([d.get(x, 0xFFFFFFFF) for x in q.tolist()], dtype=np.uint32)
+        ef = np.array([x in d for x in q.tolist()], dtype=np.uint8)
+        np.testing.assert_array_equal(f, ef)
+        np.testing.assert_array_equal(v, ev)
+
+
+def test_join_lookup64_matches_dictionary():
+    rng = np.random.default_rng(10)
+    for n, nq in [(0, 10), (3, 50), (20000, 60000)]:
+        keys = rng.integers(0, (1 << 64) - 2, size=n, dtype=np.uint64)
+        keys = np.unique(keys)
+        n = len(keys)
+        keys = rng.permutation(keys)
+        vals = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+        pool = np.concatenate([keys, rng.integers(0, 1 << 64, size=max(n, 8), dtype=np.uint64),
+                               np.array([(1 << 64) - 1, 0], dtype=np.uint64)])
+        q = pool[rng.integers(0, len(pool), size=nq)]
+        d = dict(zip(keys.tolist(), vals.tolist()))
+        v, f = oracle.join_find64(keys, vals, q)
+        ev = np.array([d.get(x, (1 << 64) - 1) for x in q.tolist()], dtype=np.uint64)
+        ef = np.array([x in d for x in q.tolist()], dtype=np.uint8)
+        np.testing.assert_array_equal(f, ef)
+        np.testing.assert_array_equal(v, ev)
+
+
 # ---------------------------------------------- build + find vs brute force
 
 GRID = [
@@ -402,6 +442,94 @@ def test_checker_catches_planted_mistakes():
     t[part_b * 16] = oracle.EMPTY64
     assert oracle.check32(params, t, keys, vals)[0] == 4
     assert full_b >= 0
+
+
+def _occupied64(t, b, bucket):
+    """Occupied slots of a 64-bit layout's bucket (key words not empty)."""
+    keys = t[2 * bucket * b:2 * (bucket + 1) * b:2]
+    return int(np.sum(keys != np.uint64(oracle.EMPTY64)))
+
+
+def test_checker64_catches_planted_mistakes():
+    """orc_check64 on a valid serial 64-bit layout, then with one mistake
+    planted per copy; each returns the number of the invariant it breaks
+    (Section III: every pair stored once with its value, in a candidate
+    bucket, buckets filled as a prefix, empty slots wholly empty)."""
+    n, b = 3000, 8
+    keys, vals = datagen.unique_keys64(n, 5), datagen.values64(n, 5)
+    params = oracle.params_for("bcht", n, 0.9, 5, b=b, wide=True)
+    st, table, _ = oracle.build64(params, keys, vals)
+    assert st == oracle.OK
+    assert oracle.check64(params, table, keys, vals) == (0, "ok")
+    E = np.uint64(oracle.EMPTY64)
+    m = params.m
+    loads = [_occupied64(table, b, bk) for bk in range(m)]
+    part = [bk for bk in range(m) if 1 < loads[bk] < b]
+    assert part, "the layout has no partly filled bucket"
+    # I1: a dropped pair (the last one of a bucket, so no hole appears)
+    bk = part[0]
+    s = bk * b + loads[bk] - 1
+    t = table.copy(); t[2 * s] = E; t[2 * s + 1] = E
+    assert oracle.check64(params, t, keys, vals)[0] == 1
+    # I1: a changed value word
+    t = table.copy(); t[2 * (bk * b) + 1] ^= np.uint64(1 << 63)
+    assert oracle.check64(params, t, keys, vals)[0] == 1
+    # I1: a duplicated key (one stored pair copied over another)
+    occ = [bb * b + i for bb in range(m) for i in range(loads[bb])]
+    t = table.copy(); t[2 * occ[1]:2 * occ[1] + 2] = table[2 * occ[0]:2 * occ[0] + 2]
+    assert oracle.check64(params, t, keys, vals)[0] == 1
+    # I1: a slot left holding the slot-lock key (2^64 - 2) in place of its key
+    t = table.copy(); t[2 * occ[3]] = np.uint64(oracle.EMPTY64 - 1)
+    assert oracle.check64(params, t, keys, vals)[0] == 1
+    # I6: the empty key with a value word
+    empty = next(bb * b + loads[bb] for bb in range(m) if loads[bb] < b)
+    t = table.copy(); t[2 * empty + 1] = np.uint64(12345)
+    assert oracle.check64(params, t, keys, vals)[0] == 6
+    # I4: a hole inside a bucket
+    t = table.copy()
+    ld = loads[bk]
+    t[2 * (bk * b + ld):2 * (bk * b + ld) + 2] = t[2 * bk * b:2 * bk * b + 2]
+    t[2 * bk * b] = E; t[2 * bk * b + 1] = E
+    assert oracle.check64(params, t, keys, vals)[0] == 4
+    # I2: a pair moved to a bucket none of its hashes names (Python big-int
+    # hashes, independent of the oracle's)
+    src = occ[7]
+    k = int(table[2 * src])
+    cands = {((params.a[i] * k + params.c[i]) % P61) % m for i in range(3)}
+    dst = next(bb for bb in range(m) if bb not in cands and loads[bb] < b)
+    t = table.copy()
+    t[2 * (dst * b + loads[dst]):2 * (dst * b + loads[dst]) + 2] = table[2 * src:2 * src + 2]
+    sb = src // b
+    last = sb * b + loads[sb] - 1
+    t[2 * src:2 * src + 2] = t[2 * last:2 * last + 2]
+    t[2 * last] = E; t[2 * last + 1] = E
+    assert oracle.check64(params, t, keys, vals)[0] == 2
+
+
+@pytest.mark.parametrize("via", [1, 2])
+def test_checker64_catches_early_exit_violation(via):
+    """A key stored in the bucket of hash `via` while the bucket of hash 0
+    has room breaks I3, the property early-exit lookups rely on."""
+    b, m = 8, 5
+    a, c = datagen.hash_constants64(9, 3)
+    params = oracle.Params(scheme="bcht", b=b, m=m, h=3, a=a, c=c)
+
+    def H(i, k):
+        return ((a[i] * k + c[i]) % P61) % m
+
+    k = next(k for k in range(1, 1 << 20)
+             if len({H(0, k), H(1, k), H(2, k)}) == 3)
+    t = oracle.empty_table(params, wide=True)
+    slot = H(via, k) * b
+    t[2 * slot] = np.uint64(k); t[2 * slot + 1] = np.uint64(77)
+    keys = np.array([k], dtype=np.uint64)
+    vals = np.array([77], dtype=np.uint64)
+    assert oracle.check64(params, t, keys, vals)[0] == 3
+    # the same key in its first bucket is valid
+    t = oracle.empty_table(params, wide=True)
+    slot = H(0, k) * b
+    t[2 * slot] = np.uint64(k); t[2 * slot + 1] = np.uint64(77)
+    assert oracle.check64(params, t, keys, vals) == (0, "ok")
 
 
 def test_checker_catches_early_exit_violation():
