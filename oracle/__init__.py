@@ -83,6 +83,10 @@ def lib():
             getattr(_lib, name).argtypes = [p, p, p, u64, p, p]
         _lib.orc_insert32.restype = ctypes.c_int
         _lib.orc_insert32.argtypes = [p, p, u32, u32, p, p]
+        _lib.orc_exchange32.restype = ctypes.c_int
+        _lib.orc_exchange32.argtypes = [p, p, u32, u32, p, p, p]
+        _lib.orc_continue32.restype = ctypes.c_int
+        _lib.orc_continue32.argtypes = [p, p, u32, u32, u64, u32, p, p]
         _lib.orc_find32.argtypes = [p, p, p, u64, p, p, p, p]
         _lib.orc_find64.argtypes = [p, p, p, u64, p, p, p, p]
         _lib.orc_brute_find32.argtypes = [p, p, u64, p, u64, p, p]
@@ -195,6 +199,30 @@ def insert32(params: Params, table: np.ndarray, key: int, val: int, rng_state: i
     probes = ctypes.c_uint64(0)
     st = lib().orc_insert32(ctypes.byref(pc), _ptr(table), key, val, ctypes.byref(rng),
                             ctypes.byref(probes))
+    return st, rng.value, probes.value
+
+
+def exchange32(params: Params, table: np.ndarray, key: int, val: int, rng_state: int):
+    """First cuckoo step of inserting (key, val) whose first bucket is full:
+    exchange with a random slot there (table modified in place).  Returns
+    (status, new rng state, evicted key, evicted value)."""
+    pc = params.to_c()
+    rng = ctypes.c_uint32(rng_state)
+    ek, ev = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    st = lib().orc_exchange32(ctypes.byref(pc), _ptr(table), key, val, ctypes.byref(rng),
+                              ctypes.byref(ek), ctypes.byref(ev))
+    return st, rng.value, ek.value, ev.value
+
+
+def continue32(params: Params, table: np.ndarray, key: int, val: int, from_bucket: int,
+               chain: int, rng_state: int):
+    """Rest of the insertion of a pair just evicted from bucket from_bucket
+    after `chain` exchanges.  Returns (status, new rng state, bucket reads)."""
+    pc = params.to_c()
+    rng = ctypes.c_uint32(rng_state)
+    probes = ctypes.c_uint64(0)
+    st = lib().orc_continue32(ctypes.byref(pc), _ptr(table), key, val, from_bucket, chain,
+                              ctypes.byref(rng), ctypes.byref(probes))
     return st, rng.value, probes.value
 
 

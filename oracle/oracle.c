@@ -130,18 +130,13 @@ static int check_params(const orc_params* p) {
 
 /* ------------------------------------------------------------ insertion */
 
-/* Bucketed cuckoo insertion (Section III-A; Section V-B, BCHT insertion).
- * Start at H0.  A bucket with a free slot takes the pair at slot = load
- * (inserts fill each bucket as a prefix).  A full bucket exchanges the
- * carried pair with a random resident; the evicted pair continues at the
- * hash after the one that placed it there, that index being the lowest i
- * with H_i(key) equal to the bucket it left (footnote to Section III-A).
- * Reaching the eviction cap with a full bucket fails the build. */
-static int insert_cuckoo32(const orc_params* p, uint64_t* t, uint32_t k, uint32_t v,
-                           uint32_t* rng, uint64_t* probes) {
-  uint64_t cur = pack(k, v);
-  bucket_ref B = bucket32(p, 0, k);
-  uint32_t chain = 0;
+/* The cuckoo walk of Section III-A from bucket B with `chain` exchanges
+ * already made: the carried pair takes slot = load of a bucket with room;
+ * at a full bucket it exchanges with a random slot and the evicted pair
+ * continues at H_{(j+1) mod h}, j the lowest index whose hash names the
+ * bucket it left; a full bucket met after max_chain exchanges fails. */
+static int cuckoo_walk32(const orc_params* p, uint64_t* t, uint64_t cur, bucket_ref B,
+                         uint32_t chain, uint32_t* rng, uint64_t* probes) {
   for (;;) {
     (*probes)++;
     uint32_t load = load32(t, B);
@@ -161,6 +156,18 @@ static int insert_cuckoo32(const orc_params* p, uint64_t* t, uint32_t k, uint32_
     B = bucket32(p, (j + 1) % p->h, key_of(cur));
     chain++;
   }
+}
+
+/* Bucketed cuckoo insertion (Section III-A; Section V-B, BCHT insertion).
+ * Start at H0.  A bucket with a free slot takes the pair at slot = load
+ * (inserts fill each bucket as a prefix).  A full bucket exchanges the
+ * carried pair with a random resident; the evicted pair continues at the
+ * hash after the one that placed it there, that index being the lowest i
+ * with H_i(key) equal to the bucket it left (footnote to Section III-A).
+ * Reaching the eviction cap with a full bucket fails the build. */
+static int insert_cuckoo32(const orc_params* p, uint64_t* t, uint32_t k, uint32_t v,
+                           uint32_t* rng, uint64_t* probes) {
+  return cuckoo_walk32(p, t, pack(k, v), bucket32(p, 0, k), 0, rng, probes);
 }
 
 /* Load-balanced bucketed cuckoo insertion (Section III-A: the variation
@@ -268,6 +275,33 @@ int orc_insert32(const orc_params* p, uint64_t* table, uint32_t key, uint32_t va
   if (p->scheme == ORC_IHT) return insert_iceberg32(p, table, key, val, probes);
   if (p->scheme == ORC_BCHT_LB) return insert_lb32(p, table, key, val, rng, probes);
   return insert_cuckoo32(p, table, key, val, rng, probes);
+}
+
+int orc_exchange32(const orc_params* p, uint64_t* table, uint32_t key, uint32_t val,
+                   uint32_t* rng, uint32_t* ev_key, uint32_t* ev_val) {
+  if (!check_params(p) || (p->scheme != ORC_BCHT && p->scheme != ORC_CHT1)) return ORC_BADARG;
+  bucket_ref B = bucket32(p, 0, key);
+  if (load32(table, B) < B.size) return ORC_BADARG;
+  *rng = orc_xorshift32(*rng);
+  uint32_t s = *rng % B.size;
+  uint64_t victim = table[B.first_slot + s];
+  table[B.first_slot + s] = pack(key, val);
+  *ev_key = key_of(victim);
+  *ev_val = (uint32_t)(victim >> 32);
+  return ORC_OK;
+}
+
+int orc_continue32(const orc_params* p, uint64_t* table, uint32_t key, uint32_t val,
+                   uint64_t from_bucket, uint32_t chain, uint32_t* rng, uint64_t* probes) {
+  uint64_t local_probes = 0;
+  if (!probes) probes = &local_probes;
+  if (!check_params(p) || (p->scheme != ORC_BCHT && p->scheme != ORC_CHT1)) return ORC_BADARG;
+  if (from_bucket >= p->m) return ORC_BADARG;
+  uint32_t j = 0;
+  while (j < p->h && bucket32(p, j, key).first_slot != from_bucket * p->b) j++;
+  if (j == p->h) return ORC_BADARG;     /* from_bucket is none of the key's candidates */
+  return cuckoo_walk32(p, table, pack(key, val), bucket32(p, (j + 1) % p->h, key), chain, rng,
+                       probes);
 }
 
 int orc_build32(const orc_params* p, const uint32_t* keys, const uint32_t* vals,

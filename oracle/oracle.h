@@ -85,6 +85,20 @@ void orc_find64(const orc_params* p, const uint64_t* table, const uint64_t* q,
                 uint64_t nq, uint64_t* out_v, uint8_t* out_f, uint64_t* probes,
                 uint8_t* per_query_probes);
 
+/* Section III-A's cuckoo insertion split at its first exchange, to replay
+ * other schedules of the same steps (BCHT and CHT1 tables):
+ * orc_exchange32 makes the first step of inserting (key, val) when its
+ * first bucket H_0(key) is full: an exchange with a random slot (the
+ * generator advanced once), the evicted pair returned in *ev_key, *ev_val;
+ * ORC_BADARG if that bucket has room.  orc_continue32 finishes the
+ * insertion of a pair just evicted from bucket from_bucket after `chain`
+ * exchanges: it continues at H_{(j+1) mod h}, j the lowest index whose
+ * hash names from_bucket (ORC_BADARG if none does). */
+int orc_exchange32(const orc_params* p, uint64_t* table, uint32_t key, uint32_t val,
+                   uint32_t* rng, uint32_t* ev_key, uint32_t* ev_val);
+int orc_continue32(const orc_params* p, uint64_t* table, uint32_t key, uint32_t val,
+                   uint64_t from_bucket, uint32_t chain, uint32_t* rng, uint64_t* probes);
+
 /* Plain definition of a lookup over the input pairs: sort + binary search. */
 void orc_brute_find32(const uint32_t* keys, const uint32_t* vals, uint64_t n,
                       const uint32_t* q, uint64_t nq, uint32_t* out_v, uint8_t* out_f);
