@@ -5,10 +5,14 @@ iceberg table (16-slot primaries, 8-slot secondaries of 1/8 the primary
 slots, t = 16, LF 0.85) and the one-slot cuckoo table (h = 3, LF 0.8),
 built and queried as the benchmark does.
 
-The whole GPU layout goes through the oracle's invariant checker; every
-query is checked against properties that hold at any size (all positives
-found, no negative found, a half-positive batch finds exactly half); a
-sample of each batch is checked value for value against brute force."""
+Also the power-of-two-choice table (h = 2, 16-slot buckets, LF 0.82, the
+highest load it reaches reliably) and the paper's one-level iceberg table
+(t = 13 of 16 slots, LF 0.82), whose builds are the concurrent kernels.
+
+The whole GPU layout goes through the oracle's invariant checker, and every
+(found, value) result of the three query batches (100, 0 and 50% positive)
+is compared with the plain lookup definition (the oracle's sort-merge join
+of the input pairs with the queries)."""
 import numpy as np
 import pytest
 
@@ -20,29 +24,23 @@ from tests.test_gpu_schemes import iceberg_params
 pytestmark = pytest.mark.gpu
 
 N = 1 << 27
-SAMPLE = 1 << 20
 
 
 def check_batches(t, keys, vals, wide, seed):
     import torch
-    rng = np.random.default_rng(seed)
-    samples = []
+    join = oracle.join_find64 if wide else oracle.join_find32
     for frac in (1.0, 0.0, 0.5):
         q = datagen.mixed_queries(N, N, frac, seed, wide=wide)
         v, f = t.find(dev(q))
         torch.cuda.synchronize()
-        hf = host_u8(f)
-        assert int(hf.sum()) == int(frac * N), frac
-        idx = rng.choice(N, SAMPLE, replace=False)
         hv = host_u64(v) if wide else host_u32(v)
-        samples.append((q[idx], hv[idx], hf[idx]))
+        hf = host_u8(f)
         del v, f
-        print("  batch %.1f positive checked" % frac, flush=True)
-    q = np.concatenate([s[0] for s in samples])
-    brute = oracle.brute_find64 if wide else oracle.brute_find32
-    ev, ef = brute(keys, vals, q)
-    np.testing.assert_array_equal(np.concatenate([s[2] for s in samples]), ef)
-    np.testing.assert_array_equal(np.concatenate([s[1] for s in samples]), ev)
+        ev, ef = join(keys, vals, q)
+        assert int(ef.sum()) == int(frac * N), frac
+        np.testing.assert_array_equal(hf, ef)
+        np.testing.assert_array_equal(hv, ev)
+        print("  batch %.1f positive: all %d results equal" % (frac, N), flush=True)
 
 
 def test_full_size_64bit():
@@ -106,4 +104,45 @@ def test_full_size_one_slot_cuckoo():
     assert code == 0, msg
     print("  layout checked", flush=True)
     check_batches(t, keys, vals, False, 3)
+    t.close()
+
+
+def test_full_size_power_of_two():
+    import paper_2108_07232_amd as bht
+    print("full-size parity: BP2HT (b = 16, h = 2), 2^27 keys, LF 0.82", flush=True)
+    keys, vals = datagen.unique_keys(N, 4), datagen.values(N, 4)
+    for s in range(4):
+        p = oracle.params_for("bp2ht", N, 0.82, 40 + s, b=16)
+        t = bht.Table(p.m * 16, 16, "bp2ht", p.a, p.c, rng_seed=p.rng_seed)
+        st = t.build(dev(keys), dev(vals))
+        if st == bht.BHT_OK:
+            break
+        assert st == bht.BHT_ERR_BUILD_FAILED
+        t.close()
+    assert st == bht.BHT_OK
+    code, msg = oracle.check32(p, t.download(), keys, vals)
+    assert code == 0, msg
+    print("  layout checked", flush=True)
+    check_batches(t, keys, vals, False, 4)
+    t.close()
+
+
+def test_full_size_iceberg_one_level():
+    import paper_2108_07232_amd as bht
+    print("full-size parity: one-level iceberg (b = 16, t = 13), 2^27 keys, LF 0.82", flush=True)
+    keys, vals = datagen.unique_keys(N, 5), datagen.values(N, 5)
+    for s in range(4):
+        p = iceberg_params(N, 0.82, 50 + s, b=16, threshold=13)
+        t = bht.Table(p.m * p.b, p.b, p.scheme, p.a, p.c, rng_seed=p.rng_seed,
+                      iht_threshold=p.threshold)
+        st = t.build(dev(keys), dev(vals))
+        if st == bht.BHT_OK:
+            break
+        assert st == bht.BHT_ERR_BUILD_FAILED
+        t.close()
+    assert st == bht.BHT_OK
+    code, msg = oracle.check32(p, t.download(), keys, vals)
+    assert code == 0, msg
+    print("  layout checked", flush=True)
+    check_batches(t, keys, vals, False, 5)
     t.close()
