@@ -51,6 +51,13 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-log2n", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="default workload: skip the batched-mode comparison")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="default workload: skip the served-mode comparison")
+    ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--serve-rates", default="10000,50000",
+                    help="default workload: arrival rates of the served-mode comparison")
     ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--out", default=None, help="also append the JSON line to this file")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -153,20 +160,34 @@ def recorded_traffic():
 
 
 def cpu_baseline(args, n_s):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+    """The oracle, as it stands, on a bounded sample of the timed workload:
+    the first n_s of the timed keys and values (the generator's key stream
+    is the same), the same hash constants and eviction seed, a table sized
+    for them at the same load factor, and n_s queries per batch from the
+    same generator; then the small configuration (2^20 keys) three times.
+    One thread pinned to one core."""
+    import numpy as np
+
     import datagen
-    import oracle
     keys, vals = datagen.unique_keys(n_s, args.seed), datagen.values(n_s, args.seed)
     qs = {"find_pos": datagen.positive_queries(n_s, args.seed),
           "find_neg": datagen.mixed_queries(n_s, n_s, 0.0, args.seed),
           "find_mix": datagen.mixed_queries(n_s, n_s, 0.5, args.seed)}
-    params = None
+    small = 1 << 20
+    sk, sv = datagen.unique_keys(small, args.seed), datagen.values(small, args.seed)
+    sq = {"find_pos": datagen.positive_queries(small, args.seed),
+          "find_neg": datagen.mixed_queries(small, small, 0.0, args.seed),
+          "find_mix": datagen.mixed_queries(small, small, 0.5, args.seed)}
     # one thread pinned to one core (this thread only; the GPU is idle here)
     allowed = os.sched_getaffinity(0)
     core = min(allowed)
     os.sched_setaffinity(0, {core})
     try:
-        times, probes, params = _cpu_runs(args, n_s, keys, vals, qs)
+        times, _ = _cpu_runs(args, n_s, keys, vals, qs)
+        small_rates = []
+        for _ in range(3):
+            t_s, _ = _cpu_runs(args, small, sk, sv, sq)
+            small_rates.append(4 * small / sum(t_s.values()) / 1e9)
     finally:
         os.sched_setaffinity(0, allowed)
     model = None
@@ -184,15 +205,19 @@ def cpu_baseline(args, n_s):
         "unit": "Gkeys/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": "2^%d keys at LF %g (BCHT b=%d h=3), build + 2^%d queries at 100/0/50%% "
-                  "positive, serial C oracle, one thread" % (args.cpu_log2n, args.lf, args.bucket,
-                                                           args.cpu_log2n),
+        "sample": "the first 2^%d of the timed keys and values with the same hash constants, "
+                  "table sized for them at LF %g (BCHT b=%d h=3); build + 2^%d queries at "
+                  "100/0/50%% positive; serial C oracle, one thread (the whole 2^%d workload "
+                  "would take the oracle several minutes)"
+                  % (args.cpu_log2n, args.lf, args.bucket, args.cpu_log2n, args.log2n),
         "pinned_core": core,
         "host_cpu": model,
         "host_logical_cpus": os.cpu_count(),
         "seconds": {k: round(v, 3) for k, v in times.items()},
         "rates_gkeys_s": {k: round(n_s / v / 1e9, 6) for k, v in times.items()},
-    }, probes
+        "small_config_2e20": {"runs": 3, "gkeys_s_median": round(float(np.median(small_rates)), 6),
+                              "gkeys_s": [round(r, 6) for r in small_rates]},
+    }
 
 
 def _cpu_runs(args, n_s, keys, vals, qs):
@@ -212,7 +237,21 @@ def _cpu_runs(args, n_s, keys, vals, qs):
         _, _, pr, _ = oracle.find32(params, table, q)
         times[name] = time.perf_counter() - t0
         probes[name.replace("find_", "")] = pr / n_s
-    return times, probes, params
+    return times, probes
+
+
+def expected_results(n, seed, frac, vals):
+    """Expected (values, found) of every query of a benchmark batch, from the
+    generator's record of which inserted key each query is (a stored key
+    returns its value, an absent one 0xFFFFFFFF and not found)."""
+    import numpy as np
+
+    import datagen
+    src = datagen.query_sources(n, n, None if frac == 1.0 else frac, seed)
+    found = src < n
+    out = np.full(n, 0xFFFFFFFF, dtype=np.uint32)
+    out[found] = vals[src[found]]
+    return out, found.astype(np.uint8)
 
 
 SCHEME_CONFIGS = [
@@ -422,7 +461,7 @@ def run_schemes(args):
             f.write(line + "\n")
 
 
-def run_batched(args):
+def run_batched(args, steps=None, emit=True):
     """Batched workload: `tables` BCHT tables with key counts log-uniform in
     [2^10, 2^22] at LF 0.9, each followed by as many queries, 50% positive.
     The autotuner picks bucket size, tile width and item size on a sample of
@@ -470,7 +509,10 @@ def run_batched(args):
     best, table = autotune.tune(bht, torch, sample, reps=3, log=log)
     b, w, item, unroll = best
     log("autotuner choice: bucket %d, tile %d, item %d, unroll %d" % best)
-    sec, sts = autotune.time_batch(bht, torch, specs, b, w, item, unroll=unroll, reps=args.steps)
+    steps = args.steps if steps is None else steps
+    batched_lat = []
+    sec, sts = autotune.time_batch(bht, torch, specs, b, w, item, unroll=unroll, reps=steps,
+                                   all_times=batched_lat)
     failed = sum(1 for s in sts if s != bht.BHT_OK)
     found = int(out_f.sum(dtype=torch.int64).item())
     # plain per-table calls with the same configuration
@@ -479,126 +521,72 @@ def run_batched(args):
     stream = torch.cuda.current_stream()
 
     def plain():
+        # one synchronous call per table, as a caller of bht_build / bht_find would
         for t, s in zip(tables, specs):
             st = bht.bht_build(t.handle, s["keys"], s["vals"], stream=stream)
             if st == bht.BHT_OK:
                 bht.bht_find(t.handle, s["queries"], s["out_v"], s["out_f"], stream=stream)
         torch.cuda.synchronize()
 
-    plain()
-    times = []
-    for _ in range(args.steps):
+    def plain_async():
+        # every build enqueued, then each build's status read (the first read
+        # waits for all of them), every find enqueued, one final wait
+        for t, s in zip(tables, specs):
+            bht.bht_build_async(t.handle, s["keys"], s["vals"], stream=stream)
+        ok = [bht.bht_build_wait(t.handle, stream=stream) == bht.BHT_OK for t in tables]
+        for t, s, good in zip(tables, specs, ok):
+            if good:
+                bht.bht_find(t.handle, s["queries"], s["out_v"], s["out_f"], stream=stream)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plain()
-        times.append(time.perf_counter() - t0)
-    times.sort()
-    plain_sec = times[len(times) // 2]
+
+    def timed(fn):
+        fn()
+        times = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            times.append(time.perf_counter() - t0)
+        return sorted(times)[len(times) // 2], times
+
+    plain_sec, plain_all = timed(plain)
+    async_sec, async_all = timed(plain_async)
+    found_plain = int(out_f.sum(dtype=torch.int64).item())
     for t in tables:
         t.close()
     ops = 2 * total
-    line = json.dumps({
+    res = {
         "workload": "batched", "tables": count, "keys": total, "queries": total,
         "key_range_log2": [10, 22], "load_factor": 0.9, "positive_fraction": 0.5,
         "autotune": {"choice": {"bucket": b, "tile": w, "item": item, "unroll": unroll},
                      "sample_tables": len(sample),
                      "ms": {"b%d_w%d_i%d_u%d" % k: round(v * 1e3, 3) for k, v in table.items()}},
         "batched": {"seconds": round(sec, 5), "gops_s": round(ops / sec / 1e9, 3),
+                    "runs_ms": [round(x * 1e3, 3) for x in batched_lat],
                     "failed_tables": failed, "found": found},
-        "plain_per_table": {"seconds": round(plain_sec, 5), "gops_s": round(ops / plain_sec / 1e9, 3)},
-        "speedup": round(plain_sec / sec, 3),
+        "plain_per_table_sync": {"seconds": round(plain_sec, 5),
+                                 "gops_s": round(ops / plain_sec / 1e9, 3),
+                                 "runs_ms": [round(x * 1e3, 3) for x in plain_all]},
+        "plain_per_table_async": {"seconds": round(async_sec, 5),
+                                  "gops_s": round(ops / async_sec / 1e9, 3),
+                                  "runs_ms": [round(x * 1e3, 3) for x in async_all]},
+        "found_expected": int(sum(int(0.5 * x) for x in sizes.tolist())),
+        "found_plain": found_plain,
+        "speedup_vs_sync": round(plain_sec / sec, 3),
+        "speedup_vs_async": round(async_sec / sec, 3),
         "unit": "G keys+queries per second",
-    })
-    print(line, flush=True)
-    if args.out:
-        with open(args.out, "a") as f:
-            f.write(line + "\n")
+        "runs": steps,
+    }
+    if emit:
+        line = json.dumps(res)
+        print(line, flush=True)
+        if args.out:
+            with open(args.out, "a") as f:
+                f.write(line + "\n")
+    return res
 
 
-def make_serve_requests(torch, n_initial, initial_sizes, count, rate, seed, build_fraction=0.05,
-                        lookup_log2=(8, 20), table_log2=(12, 24), positive=0.7):
-    """Open-loop request stream: Poisson arrivals at `rate`; a request is a
-    build of a new table (size log-uniform in 2^table_log2) with probability
-    build_fraction, else a lookup batch (size log-uniform in 2^lookup_log2,
-    `positive` of it present) against a uniformly chosen table among the
-    initial ones and those whose builds were requested earlier."""
-    import numpy as np
-
-    import datagen
-    from paper_2108_07232_amd.serve import Request
-    dev = torch.device("cuda", 0)
-    u = datagen.uniform01(3 * count, seed, datagen.TAG_ARRIVALS).reshape(count, 3)
-    gaps = -np.log1p(-u[:, 0]) / rate
-    arrivals = np.cumsum(gaps) - gaps[0]
-    sizes_b = datagen.log_uniform_sizes(count, table_log2[0], table_log2[1], seed, datagen.TAG_SIZES)
-    sizes_l = datagen.log_uniform_sizes(count, lookup_log2[0], lookup_log2[1], seed,
-                                        datagen.TAG_SIZES + 16)
-    table_sizes = list(initial_sizes)
-    reqs = []
-    for i in range(count):
-        s = seed * 7919 + i
-        if u[i, 1] < build_fraction:
-            n = int(sizes_b[i])
-            tid = len(table_sizes)
-            ts = table_seed(seed, tid)
-            a, c = datagen.hash_constants(ts, 3)
-            keys = torch.from_numpy(datagen.unique_keys(n, ts).view(np.int32)).to(dev)
-            vals = torch.from_numpy(datagen.values(n, ts).view(np.int32)).to(dev)
-            reqs.append(Request("build", float(arrivals[i]), tid, keys=keys, vals=vals,
-                                capacity=datagen.capacity_for(n, 0.9), a=tuple(a), c=tuple(c),
-                                rng_seed=datagen.rng_seed(ts)))
-            table_sizes.append(n)
-        else:
-            tid = min(int(u[i, 2] * len(table_sizes)), len(table_sizes) - 1)
-            n_q = int(sizes_l[i])
-            q = datagen.mixed_queries(table_sizes[tid], n_q, positive, table_seed(seed, tid),
-                                      shuffle_seed=s)
-            qd = torch.from_numpy(q.view(np.int32)).to(dev)
-            reqs.append(Request("lookup", float(arrivals[i]), tid, queries=qd,
-                                out_v=torch.empty(n_q, dtype=torch.int32, device=dev),
-                                out_f=torch.empty(n_q, dtype=torch.uint8, device=dev)))
-    return reqs
-
-
-def table_seed(seed, tid):
-    return seed * 1000003 + 17 * tid + 5
-
-
-def build_initial_tables(torch, bht, count, seed, log2_range=(12, 24)):
-    """The resident set: `count` tables, sizes log-uniform in 2^log2_range,
-    built with one batched pass.  Returns (tables, sizes)."""
-    import numpy as np
-
-    import datagen
-    dev = torch.device("cuda", 0)
-    sizes = datagen.log_uniform_sizes(count, log2_range[0], log2_range[1], seed).tolist()
-    tables, entries, keep = [], [], []
-    for tid, n in enumerate(sizes):
-        ts = table_seed(seed, tid)
-        a, c = datagen.hash_constants(ts, 3)
-        t = bht.Table(datagen.capacity_for(n, 0.9), 16, "bcht", a, c, rng_seed=datagen.rng_seed(ts))
-        k = torch.from_numpy(datagen.unique_keys(n, ts).view(np.int32)).to(dev)
-        v = torch.from_numpy(datagen.values(n, ts).view(np.int32)).to(dev)
-        keep.append((k, v))
-        tables.append(t)
-        entries.append((t.handle, k, v, None, None, None))
-    batch = bht.bht_batch_create(entries)
-    bht.bht_batch_run(batch)
-    rc, sts = bht.bht_batch_wait(batch, count)
-    bht.bht_batch_destroy(batch)
-    for tid, st in enumerate(sts):
-        retry = 0
-        while st != bht.BHT_OK:
-            retry += 1
-            a, c = datagen.hash_constants(table_seed(seed, tid) + 7919 * retry, 3)
-            bht.bht_reseed(tables[tid].handle, bht.make_params(a, c))
-            st = tables[tid].build(*keep[tid])
-    del keep
-    torch.cuda.synchronize()
-    return tables, sizes
-
-
-def run_serve(args):
+def run_serve(args, rates=None, emit=True):
     """Serving workload: resident tables under an HBM budget, a Poisson
     request stream (5% builds, 95% lookups) at each rate, served by the
     continuous-batching loop and, as the baseline, one request at a time."""
@@ -607,10 +595,17 @@ def run_serve(args):
     import paper_2108_07232_amd as bht
     from paper_2108_07232_amd import serve
 
-    rates = [float(x) for x in args.rates.split(",")]
+    import datagen
+    from datagen import workloads
+
+    rates = [float(x) for x in (args.rates if rates is None else rates).split(",")]
     log("serve: building %d resident tables" % args.initial_tables)
     t0 = time.time()
-    tables, sizes = build_initial_tables(torch, bht, args.initial_tables, args.seed)
+    specs = workloads.initial_tables(args.initial_tables, args.seed)
+    tables = serve.build_resident_tables(
+        torch, specs, workloads.table_data,
+        reseed=lambda sp, k: datagen.hash_constants(sp["seed"] + 7919 * k, 3))
+    sizes = [sp["n"] for sp in specs]
     resident_bytes = sum(t.info[3] for t in tables)
     log("resident set ready: %.2f GB, %d keys (%.1f s)" % (resident_bytes / 1e9, sum(sizes),
                                                            time.time() - t0))
@@ -618,8 +613,9 @@ def run_serve(args):
            "resident_gb": round(resident_bytes / 1e9, 3), "budget_gb": args.budget_gb,
            "requests_per_rate": args.requests, "rates": {}}
     for rate in rates:
-        reqs = make_serve_requests(torch, args.initial_tables, sizes, args.requests, rate,
-                                   args.seed + int(rate))
+        stream_spec = workloads.request_stream(sizes, args.requests, rate, args.seed + int(rate),
+                                               tables_seed=args.seed)
+        reqs = serve.make_requests(torch, stream_spec, workloads.table_data)
         work = sum((r.queries.numel() if r.kind == "lookup" else r.keys.numel()) for r in reqs)
         entry = {}
         for mode in ("continuous", "serial"):
@@ -666,11 +662,13 @@ def run_serve(args):
         torch.cuda.empty_cache()
     for t in tables:
         t.close()
-    line = json.dumps(out)
-    print(line, flush=True)
-    if args.out:
-        with open(args.out, "a") as f:
-            f.write(line + "\n")
+    if emit:
+        line = json.dumps(out)
+        print(line, flush=True)
+        if args.out:
+            with open(args.out, "a") as f:
+                f.write(line + "\n")
+    return out
 
 
 SUCCESS_SWEEP = [
@@ -1067,6 +1065,31 @@ def main():
         run_schemes(args)
         return
 
+    import torch
+    torch.cuda.set_device(0)
+    result = run_headline(args)
+    if not args.no_batched:
+        try:
+            result["batched"] = run_batched(args, steps=args.batched_steps, emit=False)
+        except Exception as e:          # the headline line is still printed
+            result["batched"] = {"error": "%s: %s" % (type(e).__name__, e)}
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        try:
+            result["serve"] = run_serve(args, rates=args.serve_rates, emit=False)
+        except Exception as e:
+            result["serve"] = {"error": "%s: %s" % (type(e).__name__, e)}
+    line = json.dumps(result)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "a") as f:
+            f.write(line + "\n")
+
+
+def run_headline(args):
+    """The headline workload: build + three query batches per step, timed;
+    then, untimed, every result of the last step checked, probe counts taken
+    on the timed layout, the ceilings and the CPU baseline."""
     import numpy as np
     import torch
 
@@ -1074,7 +1097,6 @@ def main():
     import paper_2108_07232_amd as bht
 
     n = 1 << args.log2n
-    torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     log("generating inputs: 2^%d keys" % args.log2n)
     t0 = time.time()
@@ -1083,12 +1105,14 @@ def main():
     queries = {"find_pos": datagen.positive_queries(n, args.seed),
                "find_neg": datagen.mixed_queries(n, n, 0.0, args.seed),
                "find_mix": datagen.mixed_queries(n, n, 0.5, args.seed)}
+    fracs = {"find_pos": 1.0, "find_neg": 0.0, "find_mix": 0.5}
     d_keys = torch.from_numpy(keys.view(np.int32)).to(dev)
     d_vals = torch.from_numpy(vals.view(np.int32)).to(dev)
     d_q = {k: torch.from_numpy(v.view(np.int32)).to(dev) for k, v in queries.items()}
-    del keys, vals, queries
-    out_v = torch.empty(n, dtype=torch.int32, device=dev)
-    out_f = torch.empty(n, dtype=torch.uint8, device=dev)
+    del keys, queries
+    # one output pair per batch, so every result of the last step can be checked
+    out = {k: (torch.empty(n, dtype=torch.int32, device=dev),
+               torch.empty(n, dtype=torch.uint8, device=dev)) for k in fracs}
     torch.cuda.synchronize()
     log("inputs resident in HBM (%.1f s)" % (time.time() - t0))
 
@@ -1129,7 +1153,7 @@ def main():
         find_kernel_ms = {}
         for name in ("find_pos", "find_neg", "find_mix"):
             e[name][0].record(stream)
-            bht.bht_find(table.handle, d_q[name], out_v, out_f, stream=stream)
+            bht.bht_find(table.handle, d_q[name], out[name][0], out[name][1], stream=stream)
             e[name][1].record(stream)
         torch.cuda.synchronize()
         for name in ("find_pos", "find_neg", "find_mix"):
@@ -1163,63 +1187,99 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    # correctness spot check of the last step's mixed batch against the
-    # generator's membership (positives found, negatives absent)
-    found_mix = int(out_f.sum().item())
+    # every result of the last step against the generator's record of which
+    # inserted key (if any) each query is
+    log("checking every result of the last step")
+    mismatches = {}
+    for name, frac in fracs.items():
+        ev_, ef_ = expected_results(n, args.seed, frac, vals)
+        hv = out[name][0].cpu().numpy().view(np.uint32)
+        hf = out[name][1].cpu().numpy()
+        mismatches[name] = int(np.count_nonzero((hv != ev_) | (hf != ef_)))
+        del ev_, ef_, hv, hf
+    verified = {"queries_checked": 3 * n, "mismatches": mismatches,
+                "ok": all(v == 0 for v in mismatches.values())}
+    part, evicted, ovf_probes = bht.bht_build_stats(table.handle)
 
+    # probe counts of the timed layout: the instrumented find (untimed) on
+    # each batch; the counts sum into the table's counter as well
+    log("probe counts on the timed layout")
+    probes_buf = torch.empty(n, dtype=torch.uint8, device=dev)
+    sv, sf = torch.empty_like(out["find_pos"][0]), torch.empty_like(out["find_pos"][1])
+    probes = {}
+    bht.bht_get_probe_stats(table.handle)
+    for name in fracs:
+        bht.bht_find_counted(table.handle, d_q[name], sv, sf, probes_buf, stream=stream)
+        probes[name.replace("find_", "")] = int(probes_buf.sum(dtype=torch.int64).item()) / n
+        if not (torch.equal(sv, out[name][0]) and torch.equal(sf, out[name][1])):
+            verified["ok"] = False
+            verified["counted_find_differs"] = name
+    _, find_total = bht.bht_get_probe_stats(table.handle)
+    verified["probe_stats_total_matches"] = find_total == round(sum(probes.values()) * n)
     ceilings = measure_ceilings(bht, table, torch, stream) if not args.no_ceilings else None
+    # insertion probes of the paper's concurrent insertion on the same input
+    # (the cost model's P_ins; this rebuilds the table, after everything above)
+    bht.bht_set_tuning(table.handle, 0, 0, 0, "concurrent")
+    counter = torch.zeros(1, dtype=torch.int64, device=dev)
+    st = bht.bht_build_counted(table.handle, d_keys, d_vals, counter, stream=stream)
+    probes["insert"] = (bht.bht_get_probe_stats(table.handle)[0] / n) if st == bht.BHT_OK else None
+    del probes_buf, sv, sf, out, d_q, d_keys, d_vals
+    table.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    del vals
 
     kernel_ms = {k: float(np.mean(v)) for k, v in rec.items()}
-    step_ms = rec
     cpu = None
-    probes = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on 2^%d keys" % args.cpu_log2n)
-        cpu, probes = cpu_baseline(args, 1 << args.cpu_log2n)
-    part, evicted, ovf_probes = bht.bht_build_stats(table.handle)
+        cpu = cpu_baseline(args, 1 << args.cpu_log2n)
     build_stats = None
     if part:
         build_stats = {"passes": partition_passes(m, b), "slots_per_key": m * b / n,
                        "evicted_per_key": evicted / n, "overflow_probes_per_key": ovf_probes / n}
-    bytes_per = algorithmic_bytes(probes, build_stats) if probes else None
+    bytes_per = algorithmic_bytes(probes, build_stats)
 
     kernels = {}
     for name in ("build", "find_pos", "find_neg", "find_mix"):
         ms = kernel_ms[name]
-        entry = {"ms": round(ms, 4), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 4),
-                 "ms_median": round(float(np.median(step_ms[name])), 4),
-                 "ms_min": round(float(np.min(step_ms[name])), 4)}
-        if bytes_per:
-            gbs = bytes_per[name] * n / (ms * 1e-3) / 1e9
-            entry.update({"bytes_per_key": round(bytes_per[name], 2), "achieved_gbs": round(gbs, 1),
-                          "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
-        kernels[name] = entry
-    if probes and build_stats:
-        # the same rate priced with the concurrent insertion's bytes per key
-        # (the paper's cost model), which the partitioned order avoids moving
+        gbs = bytes_per[name] * n / (ms * 1e-3) / 1e9
+        kernels[name] = {"ms": round(ms, 4), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 4),
+                         "ms_median": round(float(np.median(rec[name])), 4),
+                         "ms_min": round(float(np.min(rec[name])), 4),
+                         "bytes_per_key": round(bytes_per[name], 2),
+                         "achieved_gbs": round(gbs, 1),
+                         "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    kernels["build"]["bytes_basis"] = ("partitioned build's own traffic: radix passes, placement, "
+                                       "evicted pairs, overflow insertion" if build_stats else
+                                       "concurrent insertion: pair + probes x (bucket + write)")
+    if probes.get("insert") and build_stats:
+        # for comparison only: the same rate priced by the paper's cost model
+        # of the concurrent insertion (bytes the partitioned order avoids)
         paper = algorithmic_bytes(probes)["build"] + 8 * build_stats["slots_per_key"]
-        gbs = paper * n / (kernel_ms["build"] * 1e-3) / 1e9
-        kernels["build"].update({"paper_model_bytes_per_key": round(paper, 2),
-                                 "paper_model_gbs": round(gbs, 1),
-                                 "paper_model_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        kernels["build"]["paper_cost_model"] = {
+            "bytes_per_key": round(paper, 2),
+            "equivalent_gbs": round(paper * n / (kernel_ms["build"] * 1e-3) / 1e9, 1),
+            "note": "the concurrent insertion's bytes per key at this rate; not a traffic figure"}
     dominant = max(("build", "find_pos", "find_neg", "find_mix"), key=lambda k: kernel_ms[k])
-    roofline = None
-    if bytes_per:
-        ach = kernels[dominant]["achieved_gbs"]
-        traffic = None
-        recorded = recorded_traffic()
-        if recorded and recorded.get("n") == n and dominant in recorded:
-            traffic = recorded[dominant]
-        roofline = {"bound": "hbm", "kernel": dominant, "achieved": ach, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic}
-        if traffic:
-            roofline["traffic_gbs"] = round(traffic / (kernel_ms[dominant] * 1e-3) / 1e9, 1)
-        if ceilings:
-            roofline["gather128_ceiling_gbs"] = ceilings["gather128_gbs"]
+    ach = kernels[dominant]["achieved_gbs"]
+    traffic = None
+    recorded = recorded_traffic()
+    if recorded and recorded.get("n") == n and dominant in recorded:
+        traffic = recorded[dominant]
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_unit": kernels[dominant]["bytes_per_key"],
+                "units_per_launch": n,
+                "probes_source": "instrumented find on the timed layout"}
+    if traffic:
+        roofline["traffic_gbs"] = round(traffic / (kernel_ms[dominant] * 1e-3) / 1e9, 1)
+    if ceilings:
+        roofline["gather128_ceiling_gbs"] = ceilings["gather128_gbs"]
 
     total_ops = args.steps * 4 * n
-    result = {
-        "metric": "Gkeys/s build + Gqueries/s (pos/neg) at LF 0.9",
+    return {
+        "metric": "Gkeys/s build + Gqueries/s (pos/neg) at LF 0.9; batched/served vs plain; p99",
         "value": round(total_ops / wall / 1e9, 4),
         "unit": "Gkeys/s",
         "n_gpus": 1,
@@ -1245,21 +1305,15 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ceilings": ceilings,
-        "probes_per_key_oracle": {k: round(v, 4) for k, v in probes.items()} if probes else None,
+        "verified": verified,
+        "probes_per_key": {k: (round(v, 4) if v is not None else None) for k, v in probes.items()},
         "build_path": "partitioned" if part else "concurrent",
         "build_stats": {k: round(v, 5) for k, v in build_stats.items()} if build_stats else None,
         "build_failures": failures,
-        "mixed_found": found_mix,
         "paper_context": {"hardware": "NVIDIA TITAN V", "build_gkeys_s": 1.34438,
                           "find_pos_gq_s": 3.79958, "find_neg_gq_s": 2.35995,
                           "find_mix_gq_s": 2.92174, "source": "Table III, BCHT b=16, LF 0.9"},
     }
-    line = json.dumps(result)
-    print(line, flush=True)
-    if args.out:
-        with open(args.out, "a") as f:
-            f.write(line + "\n")
-    table.close()
 
 
 if __name__ == "__main__":

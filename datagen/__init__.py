@@ -103,6 +103,7 @@ def _native():
         _lib.dg_permutation.argtypes = [p, u64, p]
         _lib.dg_queries32.argtypes = [p, p, u64, p, u64, u64, ctypes.c_int, p]
         _lib.dg_queries64.argtypes = [p, p, u64, p, u64, u64, ctypes.c_int, p]
+        _lib.dg_query_sources.argtypes = [p, u64, p, u64, u64, ctypes.c_int, p]
     return _lib
 
 
@@ -200,6 +201,26 @@ def mixed_queries(n: int, count: int, positive_fraction: float, seed: int,
     if npos > 0 and n == 0:
         raise ValueError("positive queries requested from an empty key set")
     return _queries(n, count, npos, seed, True, wide, shuffle_seed)
+
+
+def query_sources(n: int, count: int, positive_fraction, seed: int,
+                  shuffle_seed=None) -> np.ndarray:
+    """Key-stream position of each query of mixed_queries(n, count, fraction,
+    seed, shuffle_seed), or of positive_queries(n, seed) when
+    positive_fraction is None: below n the query is inserted key number i
+    (its expected value is values(n, seed)[i]); from n on it is absent."""
+    ss = seed if shuffle_seed is None else shuffle_seed
+    if positive_fraction is None:
+        npos, shuffle = n, False
+        assert count == n
+    else:
+        npos, shuffle = int(math.floor(positive_fraction * count)), True
+    rk_pos, rk_mix = _round_keys(ss, TAG_PERM), _round_keys(ss, TAG_MIX)
+    out = np.empty(count, dtype=np.int64)
+    if count:
+        _native().dg_query_sources(_ptr(rk_pos), n, _ptr(rk_mix), count, npos, int(shuffle),
+                                   _ptr(out))
+    return out
 
 
 def hash_constants(seed: int, h: int):

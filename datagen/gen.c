@@ -147,6 +147,20 @@ void dg_queries32(const uint32_t rk_keys[4], const uint64_t rk_pos[4], uint64_t 
   }
 }
 
+/* Key-stream position of every query dg_queries32/64 emit with the same
+ * arguments: below n the query is inserted key number idx, from n on it is
+ * an absent key.  Lets a caller state every expected lookup result from the
+ * input arrays alone. */
+void dg_query_sources(const uint64_t rk_pos[4], uint64_t n, const uint64_t rk_mix[4],
+                      uint64_t count, uint64_t npos, int shuffle, uint64_t* out) {
+  const int hn = half_bits(n ? n : 1), hc = half_bits(count ? count : 1);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < (int64_t)count; i++) {
+    uint64_t j = shuffle ? perm_at((uint64_t)i, count, rk_mix, hc) : (uint64_t)i;
+    out[i] = (j < npos) ? perm_at(j % n, n, rk_pos, hn) : n + (j - npos);
+  }
+}
+
 void dg_queries64(const uint64_t rk_keys[4], const uint64_t rk_pos[4], uint64_t n,
                   const uint64_t rk_mix[4], uint64_t count, uint64_t npos, int shuffle,
                   uint64_t* out) {

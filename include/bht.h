@@ -205,9 +205,10 @@ bht_status bht_find(const bht_table* t, const uint32_t* d_queries, uint64_t n,
  * 2^64 - 2 are reserved (SENTINEL_KEY).  bht_build64 is synchronous like
  * bht_build and follows the table's build_mode: the partitioned path takes
  * builds of at least 2^18 pairs under BHT_BUILD_AUTO (workspace of about
- * 16 bytes per pair), and its on-chip step exchanges 16-byte pairs in
- * rounds ranked by each bucket's load counter, again the serial algorithm
- * of Section III-A in one insertion order. */
+ * 16 bytes per pair): each bucket's first-choice pairs are placed on chip,
+ * the pairs meeting a full first bucket exchange themselves with random
+ * residents in rounds ranked by the bucket's load counter, and the evicted
+ * pairs then continue their cuckoo chains (Section III-A) concurrently. */
 bht_status bht_build64(bht_table* t, const uint64_t* d_keys, const uint64_t* d_values,
                        uint64_t n, void* stream);
 bht_status bht_find64(const bht_table* t, const uint64_t* d_queries, uint64_t n,
@@ -215,8 +216,11 @@ bht_status bht_find64(const bht_table* t, const uint64_t* d_queries, uint64_t n,
 
 /* Instrumented variants counting probes, a probe being one bucket read
  * (Section VII-E).  bht_build_counted adds the build's bucket reads to
- * *d_probe_total (device uint64).  bht_find_counted writes each query's
- * bucket reads to d_probes[i] (device uint8).  Not meant for timing. */
+ * *d_probe_total (device uint64) and is synchronous; it always takes the
+ * concurrent kernel, on which the paper's insertion probe count is
+ * defined.  bht_find_counted writes each query's bucket reads to
+ * d_probes[i] (device uint8) and also adds their sum to a counter the table
+ * keeps (read by bht_get_probe_stats).  Not meant for timing. */
 bht_status bht_build_counted(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,
                              uint64_t n, uint64_t* d_probe_total, void* stream);
 bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint64_t n,
@@ -227,6 +231,13 @@ bht_status bht_find_counted(const bht_table* t, const uint32_t* d_queries, uint6
 bht_status bht_find64_counted(const bht_table* t, const uint64_t* d_queries, uint64_t n,
                               uint64_t* d_out_values, uint8_t* d_out_found, uint8_t* d_probes,
                               void* stream);
+/* Probe totals of a table (Section VII-E): *build_probes = bucket reads of
+ * its last build if that build was bht_build_counted, else 0;
+ * *find_probes = bucket reads of every instrumented find (32- or 64-bit)
+ * on it since the previous bht_get_probe_stats call, or since bht_create.
+ * Waits for all work on the device first.  Divide by the keys or queries
+ * involved for the paper's per-key averages. */
+bht_status bht_get_probe_stats(const bht_table* t, uint64_t* build_probes, uint64_t* find_probes);
 
 /* Tuning (speed only, never results).  tile_width: lanes that read one
  * bucket together (1 for bucket_size 1; 4, 8 or 16 otherwise, at most
@@ -244,14 +255,18 @@ bht_status bht_find64_counted(const bht_table* t, const uint64_t* d_queries, uin
  * kernel (Section V-B); BHT_BUILD_PARTITIONED first groups the pairs by the
  * region of their first bucket (two streaming radix passes), places each
  * region's pairs in their first bucket in on-chip memory, writes the
- * buckets whole, and runs the cuckoo kernel only on the pairs whose first
- * bucket was full: the serial algorithm of Section III-A in one particular
- * insertion order, so layouts obey the same invariants.  It allocates a
+ * buckets whole, lets each pair that met a full first bucket exchange
+ * itself with a random resident there (Section III-A's eviction step, on
+ * chip), and runs the concurrent cuckoo kernel only on the pairs evicted:
+ * their chains continue concurrently, as in the concurrent build, and
+ * since no bucket ever loses a pair the layout obeys the same invariants
+ * (every key in a candidate bucket, the early-exit property).  It allocates a
  * library-owned workspace of about 8 bytes per pair on first use (kept
  * until bht_destroy).  Iceberg tables (Section III-C) take the same path
  * with primaries filled on chip up to iht_threshold pairs and the rest
- * inserted at their secondary choices (the threshold rule in one serial
- * order).  BHT_BUILD_AUTO partitions builds of at least 2^18 pairs (2^26
+ * inserted at their secondary choices afterwards, concurrently (a pair
+ * reaches the secondary level only once its primary holds iht_threshold
+ * pairs, as the threshold rule requires).  BHT_BUILD_AUTO partitions builds of at least 2^18 pairs (2^26
  * for two-level iceberg tables, never one-level ones) into tables whose
  * memory the library owns (bht_create).
  * iht_early_exit (iceberg tables only, else UNSUPPORTED): 1 makes a find
@@ -330,10 +345,18 @@ bht_status bht_diag_cas(void* d_buf, uint64_t bytes, uint64_t n_ops, uint64_t se
  * their output arrays (all caller-owned device memory, as for bht_build and
  * bht_find).  bht_batch_create copies the table descriptors and the work
  * items (ranges of item_size pairs or queries; 0 = 8192) to the device.
- * bht_batch_run enqueues: a reset of all tables, one persistent build kernel
- * and one persistent query kernel, both pulling (table, range) items from
- * device-side queues; on a non-null stream the sequence is captured once
- * into a HIP graph and replayed by later runs on that stream.
+ * bht_batch_run enqueues a reset of the batch's queues and statuses, the
+ * build of every table and one persistent query kernel pulling (table,
+ * range) items from a device-side queue.  The build is the partitioned
+ * build of all tables at once (counting, scan and scatter kernels over
+ * (table, chunk) items, one on-chip placement per bin of any table, one
+ * overflow insertion kernel); when a table asks for BHT_BUILD_CONCURRENT or
+ * needs more than 1,024 bins it is instead a fill and one persistent
+ * concurrent build kernel pulling (table, range) items.  These are
+ * separate kernels because a kernel boundary is what makes one phase's
+ * writes visible to the next phase's plain loads on every XCD.  On a
+ * non-null stream the sequence is captured once into a HIP graph and
+ * replayed by later runs on that stream.
  * bht_batch_wait waits for the stream and writes each table's build status
  * to status_out[i] (may be NULL); it returns BHT_OK when every table built.
  * A table whose build failed holds unspecified contents and unspecified
@@ -354,6 +377,13 @@ bht_status bht_batch_create(const bht_batch_entry* entries, uint32_t count, uint
 bht_status bht_batch_run(bht_batch* b, void* stream);
 bht_status bht_batch_wait(bht_batch* b, void* stream, bht_status* status_out);
 void bht_batch_destroy(bht_batch* b);
+/* The batch in one synchronous call: create, run once (launched directly
+ * on stream, no graph), wait, destroy.  status_out[i] (may be NULL) gets
+ * table i's build status; returns BHT_OK when every table built.  The
+ * descriptors are a host array: the library reads every table's size on
+ * the host to plan the partitioning anyway. */
+bht_status bht_batch_build_find(const bht_batch_entry* entries, uint32_t count, uint32_t item_size,
+                                bht_status* status_out, void* stream);
 
 /* Coalesced lookups (serving): one launch answers many query batches on
  * many built 32-bit BCHT tables that share bucket size and tile width.  A

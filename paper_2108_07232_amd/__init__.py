@@ -97,6 +97,7 @@ _SIGS = {
     "bht_build_retry": (_st, [_p, _p, _p, _u64, _u64, _u32, ctypes.POINTER(_u32), _p]),
     "bht_find_counted": (_st, [_p, _p, _u64, _p, _p, _p, _p]),
     "bht_find64_counted": (_st, [_p, _p, _u64, _p, _p, _p, _p]),
+    "bht_get_probe_stats": (_st, [_p, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "bht_set_tuning": (_st, [_p, ctypes.POINTER(bht_tuning)]),
     "bht_get_tuning": (_st, [_p, ctypes.POINTER(bht_tuning)]),
     "bht_enable_timing": (_st, [_p, ctypes.c_int]),
@@ -114,6 +115,8 @@ _SIGS = {
     "bht_batch_run": (_st, [_p, _p]),
     "bht_batch_wait": (_st, [_p, _p, ctypes.POINTER(ctypes.c_int)]),
     "bht_batch_destroy": (None, [_p]),
+    "bht_batch_build_find": (_st, [ctypes.POINTER(bht_batch_entry), _u32, _u32,
+                                   ctypes.POINTER(ctypes.c_int), _p]),
     "bht_find_ctx_create": (_st, [_u32, _u64, _pp]),
     "bht_multi_find": (_st, [_p, ctypes.POINTER(bht_find_request), _u32, _u32, _p]),
     "bht_find_ctx_destroy": (None, [_p]),
@@ -318,6 +321,15 @@ def bht_find_counted(table, queries, out_values, out_found, probes, n=None, stre
            "bht_find_counted")
 
 
+def bht_get_probe_stats(table):
+    """(bucket reads of the last build if it was counted, bucket reads of the
+    counted finds since the previous call)."""
+    bp, fp = _u64(0), _u64(0)
+    _check(_lib.bht_get_probe_stats(table, ctypes.byref(bp), ctypes.byref(fp)),
+           "bht_get_probe_stats")
+    return bp.value, fp.value
+
+
 def bht_find64_counted(table, queries, out_values, out_found, probes, n=None, stream=None):
     n = queries.numel() if n is None else n
     _check(_lib.bht_find64_counted(table, _dptr(queries, None, "queries"), n,
@@ -407,9 +419,7 @@ def _ptr_of(t):
     return t.data_ptr() if hasattr(t, "data_ptr") else int(t)
 
 
-def bht_batch_create(entries, item_size: int = 0):
-    """entries: sequence of (table handle, keys, values, queries, out_values,
-    out_found) with device tensors (queries/outputs may be None)."""
+def _batch_entries(entries):
     arr = (bht_batch_entry * len(entries))()
     for i, (table, keys, vals, queries, out_v, out_f) in enumerate(entries):
         arr[i].table = table.value if isinstance(table, ctypes.c_void_p) else table
@@ -420,6 +430,13 @@ def bht_batch_create(entries, item_size: int = 0):
         arr[i].n_queries = 0 if queries is None else queries.numel()
         arr[i].d_out_values = _ptr_of(out_v)
         arr[i].d_out_found = _ptr_of(out_f)
+    return arr
+
+
+def bht_batch_create(entries, item_size: int = 0):
+    """entries: sequence of (table handle, keys, values, queries, out_values,
+    out_found) with device tensors (queries/outputs may be None)."""
+    arr = _batch_entries(entries)
     out = ctypes.c_void_p()
     _check(_lib.bht_batch_create(arr, len(entries), item_size, ctypes.byref(out)),
            "bht_batch_create")
@@ -441,6 +458,17 @@ def bht_batch_wait(batch, count: int, stream=None):
 
 def bht_batch_destroy(batch):
     _lib.bht_batch_destroy(batch)
+
+
+def bht_batch_build_find(entries, item_size: int = 0, stream=None):
+    """One synchronous batched build and query pass (entries as for
+    bht_batch_create).  Returns (overall status, per-table statuses)."""
+    arr = _batch_entries(entries)
+    st = (ctypes.c_int * len(entries))()
+    rc = _lib.bht_batch_build_find(arr, len(entries), item_size, st, _stream(stream))
+    if rc not in (BHT_OK, BHT_ERR_BUILD_FAILED, BHT_ERR_SENTINEL_KEY):
+        _check(rc, "bht_batch_build_find")
+    return rc, list(st)
 
 
 def bht_find_ctx_create(max_requests: int, max_items: int):

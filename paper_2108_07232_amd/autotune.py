@@ -26,11 +26,12 @@ def candidates(buckets=BUCKETS, tiles=TILES, items=ITEMS, unrolls=UNROLLS):
             if (b, w) in supported]
 
 
-def time_batch(bht, torch, specs, b, w, item, unroll=1, reps=3, stream=None):
+def time_batch(bht, torch, specs, b, w, item, unroll=1, reps=3, stream=None, all_times=None):
     """Median seconds of one batched build + query pass over the tables in
     `specs` (dicts with capacity, hash constants, device inputs and outputs),
     built with bucket size b, tile width w and query unroll.  Returns
-    (seconds, statuses)."""
+    (seconds, statuses); every run's seconds are appended to all_times if
+    it is a list."""
     tables = []
     try:
         for s in specs:
@@ -54,6 +55,8 @@ def time_batch(bht, torch, specs, b, w, item, unroll=1, reps=3, stream=None):
                     times.append(time.perf_counter() - t0)
         finally:
             bht.bht_batch_destroy(batch)
+        if all_times is not None:
+            all_times.extend(times)
         times.sort()
         return times[len(times) // 2], sts
     finally:

@@ -55,6 +55,8 @@ struct bht_table {
   bool last_partitioned;   // the last successful build took the partitioned path
   uint64_t last_evicted;   // ... and evicted this many pairs on chip
   uint64_t last_probes;    // ... and read this many buckets inserting them
+  uint64_t counted_build_probes;  // bucket reads of the last build, if it was counted
+  uint64_t find_probe_base;       // find-probe counter value at the last stats read
 };
 
 struct bht_batch {
@@ -336,6 +338,19 @@ bool pick(const bht_table* t, uint32_t w, uint32_t schedule, bool count, KernelS
   const uint32_t b2 = t->scheme == BHT_IHT ? t->params.iht_secondary_b : 0;
   return count ? pick_t<true>(t->scheme, t->b, b2, w, schedule, t->unroll, ks)
                : pick_t<false>(t->scheme, t->b, b2, w, schedule, t->unroll, ks);
+}
+
+// Running total of the bucket reads of instrumented finds: a 64-bit word in
+// the status area after the slot array (words 16-17; the build uses 0-3).
+unsigned long long* find_probe_counter(const bht_table* t) {
+  return reinterpret_cast<unsigned long long*>(t->d_status + 16);
+}
+
+bht_status add_find_probes(const uint8_t* probes, uint64_t n, const bht_table* t, hipStream_t st) {
+  const int grid = (int)std::min<uint64_t>((n + kBlock - 1) / kBlock, 1024);
+  probe_sum_kernel<<<grid, kBlock, 0, st>>>(probes, n, find_probe_counter(t));
+  HIP_TRY(hipGetLastError());
+  return BHT_OK;
 }
 
 bht_status launch_fill(bht_table* t, hipStream_t st) {
@@ -748,6 +763,7 @@ bht_status build32_enqueue(bht_table* t, const uint32_t* keys, const uint32_t* v
   hipStream_t st = as_stream(stream);
   t->built = false;
   t->pending_partitioned = false;
+  t->counted_build_probes = 0;
   if (use_partitioned(t, n, probe_total != nullptr)) return build32_partitioned(t, keys, vals, n, st);
   bht_status s = launch_fill(t, st);
   if (s != BHT_OK) return s;
@@ -840,6 +856,7 @@ bht_status find32_enqueue(const bht_table* t, const uint32_t* q, uint64_t n, uin
   HIP_TRY(hipGetLastError());
   if (t->timing) HIP_TRY(hipEventRecord(t->ev[3], st));
   mt->find_timed = t->timing;
+  if (probes) return add_find_probes(probes, n, t, st);
   return BHT_OK;
 }
 
@@ -938,6 +955,13 @@ bht_status create_common(uint64_t capacity_slots, uint32_t bucket_size, bht_sche
   }
   t->d_slots = reinterpret_cast<uint64_t*>(base);
   t->d_status = reinterpret_cast<uint32_t*>(base + g.slot_bytes);
+  // the find-probe counter starts from whatever the memory holds
+  e = hipMemcpy(&t->find_probe_base, find_probe_counter(t), 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    if (t->owns_memory) (void)hipFree(base);
+    delete t;
+    return hip_fail(e, "reading the status area");
+  }
   *out = t;
   return BHT_OK;
 }
@@ -1102,10 +1126,31 @@ bht_status bht_build_retry(bht_table* t, const void* d_keys, const void* d_value
 bht_status bht_build_counted(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,
                              uint64_t n, uint64_t* d_probe_total, void* stream) {
   if (!d_probe_total) return fail(BHT_ERR_INVALID_ARG, "null probe counter");
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  hipStream_t st = as_stream(stream);
+  uint64_t before = 0, after = 0;
+  HIP_TRY(hipMemcpyAsync(&before, d_probe_total, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
   bht_status s = build32_enqueue(t, d_keys, d_values, n,
                                  reinterpret_cast<unsigned long long*>(d_probe_total), stream);
   if (s != BHT_OK) return s;
-  return bht_build_wait(t, stream);
+  s = bht_build_wait(t, stream);
+  HIP_TRY(hipMemcpyAsync(&after, d_probe_total, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  t->counted_build_probes = after - before;
+  return s;
+}
+
+bht_status bht_get_probe_stats(const bht_table* t, uint64_t* build_probes, uint64_t* find_probes) {
+  if (!t || !build_probes || !find_probes) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  HIP_TRY(hipDeviceSynchronize());
+  uint64_t now = 0;
+  HIP_TRY(hipMemcpy(&now, find_probe_counter(t), 8, hipMemcpyDeviceToHost));
+  bht_table* mt = const_cast<bht_table*>(t);
+  *build_probes = t->counted_build_probes;
+  *find_probes = now - t->find_probe_base;
+  mt->find_probe_base = now;
+  return BHT_OK;
 }
 
 bht_status bht_find(const bht_table* t, const uint32_t* d_queries, uint64_t n,
@@ -1130,6 +1175,7 @@ bht_status bht_build64(bht_table* t, const uint64_t* d_keys, const uint64_t* d_v
   hipStream_t st = as_stream(stream);
   t->built = false;
   t->pending_partitioned = false;
+  t->counted_build_probes = 0;
   if (use_partitioned(t, n, false)) {
     bht_status s = build64_partitioned(t, d_keys, d_values, n, st);
     if (s != BHT_OK) return s;
@@ -1188,6 +1234,7 @@ bht_status find64_enqueue(const bht_table* t, const uint64_t* q, uint64_t n, uin
   HIP_TRY(hipGetLastError());
   if (t->timing) HIP_TRY(hipEventRecord(t->ev[3], st));
   mt->find_timed = t->timing;
+  if (probes) return add_find_probes(probes, n, t, st);
   return BHT_OK;
 }
 
@@ -1299,6 +1346,7 @@ bht_status bht_upload(bht_table* t, const void* host_slots, uint64_t n_stored) {
   t->built = true;
   t->pending = false;
   t->n_stored = n_stored;
+  t->counted_build_probes = 0;
   return BHT_OK;
 }
 
@@ -1596,7 +1644,10 @@ bht_status batch_launch(bht_batch* b, hipStream_t st) {
 bht_status bht_batch_run(bht_batch* b, void* stream) {
   if (!b) return fail(BHT_ERR_INVALID_ARG, "null batch");
   hipStream_t st = as_stream(stream);
-  for (bht_table* t : b->tables) t->built = false;
+  for (bht_table* t : b->tables) {
+    t->built = false;
+    t->counted_build_probes = 0;
+  }
   if (st == nullptr) return batch_launch(b, st);
   if (b->exec && b->graph_stream != st) {
     (void)hipGraphExecDestroy(b->exec);
@@ -1660,6 +1711,23 @@ void bht_batch_destroy(bht_batch* b) {
   if (b->h_status) (void)hipHostFree(b->h_status);
   if (b->d_ws) (void)hipFree(b->d_ws);
   delete b;
+}
+
+bht_status bht_batch_build_find(const bht_batch_entry* entries, uint32_t count, uint32_t item_size,
+                                bht_status* status_out, void* stream) {
+  bht_batch* b = nullptr;
+  bht_status s = bht_batch_create(entries, count, item_size, &b);
+  if (s != BHT_OK) return s;
+  for (bht_table* t : b->tables) {
+    t->built = false;
+    t->counted_build_probes = 0;
+  }
+  // one pass: the kernels go straight onto the stream, no graph is captured
+  s = batch_launch(b, as_stream(stream));
+  if (s == BHT_OK) s = bht_batch_wait(b, stream, status_out);
+  else (void)hipStreamSynchronize(as_stream(stream));
+  bht_batch_destroy(b);
+  return s;
 }
 
 bht_status bht_find_ctx_create(uint32_t max_requests, uint64_t max_items, bht_find_ctx** out) {

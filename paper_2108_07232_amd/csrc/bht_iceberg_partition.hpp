@@ -6,10 +6,10 @@
 // pair that meets a primary already holding t pairs is written back to the
 // front of its bin's input range and continues at its two secondary
 // choices in the insertion kernel below, which is the concurrent iceberg
-// insertion started after the primary step.  This is the serial insertion
-// in one order (first every pair whose primary is below t, then the rest),
-// so the threshold rule holds exactly: a pair reaches the secondary level
-// only once its primary holds t pairs.
+// insertion started after the primary step: first every pair whose primary
+// is below t takes it, then the rest run the secondary step concurrently.
+// The threshold rule holds exactly: a pair reaches the secondary level only
+// once its primary holds t pairs.
 #pragma once
 #include "bht_partition.hpp"
 #include "bht_schemes.hpp"

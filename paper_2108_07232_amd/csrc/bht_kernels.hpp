@@ -170,6 +170,25 @@ __global__ void fill_empty_kernel(uint64_t* __restrict__ slots, uint64_t words,
   if ((words & 1) && gtid == 0) slots[words - 1] = kEmptyPair;
 }
 
+// Adds the per-query probe counts of an instrumented find to a 64-bit total
+// (one block-wide sum, then one atomic per block).
+__global__ void probe_sum_kernel(const uint8_t* __restrict__ probes, uint64_t n,
+                                 unsigned long long* __restrict__ total) {
+  __shared__ unsigned long long part[kBlock / 64];
+  unsigned long long sum = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    sum += probes[i];
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+    if (t) atomicAdd(total, t);
+  }
+}
+
 // ----------------------------------------------------------- input feed
 
 // A wave consumes its range in order.  Lane i holds item base+i of chunk A

@@ -25,14 +25,15 @@
 //   3. overflow: the concurrent cuckoo insertion continues every evicted
 //      pair at its next bucket, bin by bin from a device work queue.
 //
-// Steps 2 and 3 are the serial algorithm of Section III-A executed in one
-// particular order: first every pair whose first bucket still has room
-// (placement at slot = load), then, for each pair that meets a full first
-// bucket, the exchange with a random slot and the evicted pair's onward
-// path.  Any insertion order is valid for a bulk build of an unordered list,
-// so the table satisfies every layout property of the concurrent build, and
-// lookups are unchanged.  Pair order within a bin or digit is not preserved
-// and need not be.
+// Steps 2 and 3 are Section III-A's insertion under a deferred-victim
+// schedule: every pair first claims a slot of its first bucket (at slot =
+// load); each pair that meets a full first bucket exchanges itself with a
+// random resident there, on chip, in the order of its claim; the evicted
+// pairs' cuckoo chains then run concurrently, as in the concurrent build.
+// No step ever empties a slot, so the layout properties of the concurrent
+// build hold (every key in a candidate bucket, buckets filled as prefixes,
+// the early-exit property), and lookups are unchanged.  Pair order within a
+// bin or digit is not preserved and need not be.
 #pragma once
 #include "bht_kernels.hpp"
 

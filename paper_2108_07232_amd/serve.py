@@ -293,3 +293,64 @@ def latency_stats(requests):
     return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
             "mean_ms": round(float(lat.mean()) * 1e3, 4), "completed": int(len(lat))}
+
+
+def make_requests(torch, specs, keys_of=None):
+    """Request objects with device tensors from host request specifications
+    (dictionaries with kind, arrival, table and either a `queries` uint32
+    array or a `spec` of a new table).  keys_of(spec) returns the host keys
+    and values of a build request's table."""
+    import numpy as np
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = []
+    for s in specs:
+        if s["kind"] == "build":
+            t = s["spec"]
+            k, v = keys_of(t)
+            out.append(Request("build", s["arrival"], s["table"],
+                               keys=torch.from_numpy(np.ascontiguousarray(k).view(np.int32)).to(dev),
+                               vals=torch.from_numpy(np.ascontiguousarray(v).view(np.int32)).to(dev),
+                               capacity=t["capacity"], a=tuple(t["a"]), c=tuple(t["c"]),
+                               rng_seed=t["rng_seed"]))
+        else:
+            q = np.ascontiguousarray(s["queries"]).view(np.int32)
+            n = len(q)
+            out.append(Request("lookup", s["arrival"], s["table"],
+                               queries=torch.from_numpy(q).to(dev),
+                               out_v=torch.empty(n, dtype=torch.int32, device=dev),
+                               out_f=torch.empty(n, dtype=torch.uint8, device=dev)))
+    return out
+
+
+def build_resident_tables(torch, specs, keys_of, bucket: int = 16, reseed=None):
+    """Tables for a list of table specifications (capacity, hash constants,
+    generator seed), built together with one batched launch sequence.  A
+    table whose build fails is rebuilt alone with the constants reseed(spec,
+    attempt) returns.  Returns the tables in the order of `specs`."""
+    import numpy as np
+    dev = torch.device("cuda", torch.cuda.current_device())
+    tables, entries, keep = [], [], []
+    for s in specs:
+        t = bht.Table(s["capacity"], bucket, "bcht", s["a"], s["c"], rng_seed=s["rng_seed"])
+        k, v = keys_of(s)
+        dk = torch.from_numpy(np.ascontiguousarray(k).view(np.int32)).to(dev)
+        dv = torch.from_numpy(np.ascontiguousarray(v).view(np.int32)).to(dev)
+        keep.append((dk, dv))
+        tables.append(t)
+        entries.append((t.handle, dk, dv, None, None, None))
+    batch = bht.bht_batch_create(entries)
+    bht.bht_batch_run(batch)
+    _, sts = bht.bht_batch_wait(batch, len(specs))
+    bht.bht_batch_destroy(batch)
+    for i, st in enumerate(sts):
+        attempt = 0
+        while st != bht.BHT_OK:
+            attempt += 1
+            if reseed is None or attempt > 50:
+                raise RuntimeError("table %d failed to build" % i)
+            a, c = reseed(specs[i], attempt)
+            bht.bht_reseed(tables[i].handle, bht.make_params(a, c))
+            st = tables[i].build(*keep[i])
+    del keep
+    torch.cuda.synchronize()
+    return tables

@@ -77,3 +77,42 @@ def test_queries_follow_the_key_stream():
         assert len(np.unique(q[~member])) == int((~member).sum())   # distinct negatives
     q64 = datagen.mixed_queries(n, n, 0.5, 3, wide=True)
     assert int(np.isin(q64, datagen.unique_keys64(n, 3)).sum()) == n // 2
+
+
+def test_query_sources_name_each_query_key():
+    """query_sources gives, for every query, its position in the key stream:
+    the query equals that key, positions below n are inserted keys and the
+    rest absent ones, for the positive batch and mixed batches alike."""
+    n = 3000
+    stream = datagen.unique_keys(n + 5000, 21)
+    for frac, count, shuffle_seed in ((None, n, None), (0.0, 2500, None), (0.5, 4000, 9),
+                                      (1.0, 4500, None), (0.7, 1234, 77)):
+        if frac is None:
+            q = datagen.positive_queries(n, 21)
+        else:
+            q = datagen.mixed_queries(n, count, frac, 21, shuffle_seed=shuffle_seed)
+        src = datagen.query_sources(n, len(q), frac, 21, shuffle_seed=shuffle_seed)
+        np.testing.assert_array_equal(stream[src], q)
+        npos = n if frac is None else int(np.floor(frac * count))
+        assert int((src < n).sum()) == npos
+
+
+def test_serve_workload_positives_are_table_keys():
+    from datagen import workloads
+    specs = workloads.initial_tables(6, 5, (8, 12))
+    sizes = [s["n"] for s in specs]
+    stream = workloads.request_stream(sizes, 300, 1000.0, 99, build_fraction=0.1,
+                                      lookup_log2=(4, 9), table_log2=(8, 10), tables_seed=5)
+    all_sizes = workloads.table_sizes_after(sizes, stream)
+    assert len(all_sizes) == len(sizes) + sum(r["kind"] == "build" for r in stream)
+    arrivals = [r["arrival"] for r in stream]
+    assert arrivals == sorted(arrivals) and arrivals[0] == 0.0
+    hits = total = 0
+    for r in stream:
+        if r["kind"] != "lookup":
+            continue
+        spec = workloads.table_spec(5, r["table"], all_sizes[r["table"]])
+        keys, _ = workloads.table_data(spec)
+        hits += int(np.isin(r["queries"], keys).sum())
+        total += len(r["queries"])
+    assert abs(hits / total - 0.7) < 0.01

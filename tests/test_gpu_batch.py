@@ -183,3 +183,27 @@ def test_batch_large_tables():
     bht.bht_batch_destroy(batch)
     for d in tabs:
         d["table"].close()
+
+
+def test_batch_build_find_one_call():
+    """The one-call batched entry point gives the same results as plain
+    per-table calls and the plain lookup definition, and reports a failing
+    table."""
+    import paper_2108_07232_amd as bht
+    tabs = make_tables(30, 6, 16, 51)
+    bad = tabs[4]
+    p = bad["params"]
+    bad["table"].close()
+    bad["table"] = bht.Table(bad["n"], 16, "bcht", p.a, p.c, max_chain=0)
+    entries = [(d["table"].handle, d["dk"], d["dv"], d["dq"], d["ov"], d["of"]) for d in tabs]
+    rc, sts = bht.bht_batch_build_find(entries, item_size=1024)
+    assert rc == bht.BHT_ERR_BUILD_FAILED and sts[4] == bht.BHT_ERR_BUILD_FAILED
+    assert all(s == bht.BHT_OK for i, s in enumerate(sts) if i != 4)
+    check_outputs(tabs, sts)
+    for d in tabs[::6]:
+        if d is bad:
+            continue
+        code, msg = oracle.check32(d["params"], d["table"].download(), d["keys"], d["vals"])
+        assert code == 0, msg
+    for d in tabs:
+        d["table"].close()

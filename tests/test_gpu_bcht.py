@@ -233,6 +233,40 @@ def test_build_probe_counts_near_paper():
     t.close()
 
 
+def test_probe_stats_totals():
+    """bht_get_probe_stats reports the counted build's bucket reads (as the
+    caller's counter saw them) and the sum of the per-query counts of the
+    counted finds since the previous call; the oracle's find on the GPU
+    layout gives the same find total."""
+    import torch
+    B = bht()
+    n = 1 << 17
+    keys, vals = workload(n, 14)
+    params = oracle.params_for("bcht", n, 0.9, 14)
+    t = gpu_table(params)
+    total = torch.full((1,), 1000, dtype=torch.int64, device="cuda")
+    assert B.bht_build_counted(t.handle, dev(keys), dev(vals), total) == B.BHT_OK
+    bp, fp = B.bht_get_probe_stats(t.handle)
+    assert bp == int(total.item()) - 1000 and n <= bp < 2 * n
+    assert fp == 0
+    layout = t.download()
+    expect = 0
+    for frac in (1.0, 0.0, 0.5):
+        q = datagen.mixed_queries(n, n, frac, 14)
+        out_v = torch.empty(n, dtype=torch.int32, device="cuda")
+        out_f = torch.empty(n, dtype=torch.uint8, device="cuda")
+        probes = torch.empty(n, dtype=torch.uint8, device="cuda")
+        B.bht_find_counted(t.handle, dev(q), out_v, out_f, probes)
+        B.bht_find(t.handle, dev(q), out_v, out_f)      # uncounted: adds nothing
+        expect += oracle.find32(params, layout, q)[2]
+    bp2, fp = B.bht_get_probe_stats(t.handle)
+    assert bp2 == bp and fp == expect
+    assert B.bht_get_probe_stats(t.handle) == (bp, 0)
+    assert B.bht_build(t.handle, dev(keys), dev(vals)) == B.BHT_OK
+    assert B.bht_get_probe_stats(t.handle) == (0, 0)    # the last build was not counted
+    t.close()
+
+
 # ------------------------------------------------ build with reseeding
 
 def test_build_retry_recovers_from_constants_that_cannot_build():

@@ -6,26 +6,30 @@ import pytest
 
 import datagen
 import oracle
+from datagen import workloads
 from tests._util import host_u32, host_u8
 
 pytestmark = pytest.mark.gpu
 
 
 def table_data(seed, tid, n):
-    import bench
-    ts = bench.table_seed(seed, tid)
-    return datagen.unique_keys(n, ts), datagen.values(n, ts)
+    return workloads.table_data(workloads.table_spec(seed, tid, n))
+
+
+def reseed(spec, attempt):
+    return datagen.hash_constants(spec["seed"] + 7919 * attempt, 3)
 
 
 def run_case(budget, count=400, rate=2e5, seed=7, headroom=None):
     import torch
 
-    import bench
-    import paper_2108_07232_amd as bht
     from paper_2108_07232_amd import serve
-    tables, sizes = bench.build_initial_tables(torch, bht, 12, seed, log2_range=(8, 14))
-    reqs = bench.make_serve_requests(torch, 12, sizes, count, rate, seed, build_fraction=0.1,
-                                     lookup_log2=(4, 12), table_log2=(8, 14))
+    specs = workloads.initial_tables(12, seed, log2_range=(8, 14))
+    tables = serve.build_resident_tables(torch, specs, workloads.table_data, reseed=reseed)
+    sizes = [s["n"] for s in specs]
+    stream = workloads.request_stream(sizes, count, rate, seed, build_fraction=0.1,
+                                      lookup_log2=(4, 12), table_log2=(8, 14))
+    reqs = serve.make_requests(torch, stream, workloads.table_data)
     if headroom is not None:      # budget = the resident set plus a little room
         budget = sum(t.info[3] for t in tables) + headroom
     srv = serve.Server(torch, budget, streams=3, max_batch=64, item_size=512)
