@@ -33,6 +33,13 @@ def parse():
     ap.add_argument("--initial-tables", type=int, default=512)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--runs", type=int, default=200, help="success workload: builds per load factor")
+    ap.add_argument("--success-schemes", default=None,
+                    help="success workload: comma-separated sweep names (default all)")
+    ap.add_argument("--no-gpu", action="store_true",
+                    help="success workload: only the oracle's serial builds (no GPU needed)")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="success workload: processes for the oracle's builds (0 = all cores, "
+                         "at most 16)")
     ap.add_argument("--workload", default="bcht",
                     choices=["bcht", "lfsweep", "schemes", "iceberg", "latency", "batched", "serve",
                              "success"],
@@ -976,43 +983,104 @@ def run_latency(args):
 def run_success(args):
     """Build success rate (Section VII-D): the same keys built with `runs`
     different hash-constant sets per load factor; reports the fraction that
-    succeed and the highest load factor with at least 99% success."""
-    import numpy as np
-    import torch
-
-    import datagen
-    import paper_2108_07232_amd as bht
+    succeed and the highest load factor with at least 99% success.  Unless
+    --no-cpu-baseline, the oracle's serial build runs on the same keys with
+    the same constants (its cpu_baseline leg), which separates the
+    algorithm's own failures from those the GPU's concurrency adds."""
+    sweep = [s for s in SUCCESS_SWEEP
+             if not args.success_schemes or s[0] in args.success_schemes.split(",")]
     n = 1 << args.log2n
-    dev = torch.device("cuda", 0)
-    keys = torch.from_numpy(datagen.unique_keys(n, args.seed).view(np.int32)).to(dev)
-    vals = torch.from_numpy(datagen.values(n, args.seed).view(np.int32)).to(dev)
     out = {"workload": "success", "n_keys": n, "runs_per_load_factor": args.runs, "schemes": {}}
-    for name, scheme, b, h, thr, lfs in SUCCESS_SWEEP:
-        rates = {}
-        for lf in lfs:
-            cap = datagen.capacity_for(n, lf)
-            ok = 0
-            table = None
-            for run in range(args.runs):
-                s = args.seed * 100003 + run
-                a, c = datagen.hash_constants(s, h)
-                if table is None:
-                    table = bht.Table(cap, b, scheme, a, c, rng_seed=datagen.rng_seed(s),
-                                      iht_threshold=thr)
-                else:
-                    bht.bht_reseed(table.handle, bht.make_params(a, c, rng_seed=datagen.rng_seed(s),
-                                                                 iht_threshold=thr))
-                ok += table.build(keys, vals) == bht.BHT_OK
-            table.close()
-            rates[str(lf)] = round(ok / args.runs, 4)
-            log("success %s LF %.2f: %d/%d" % (name, lf, ok, args.runs))
-        good = [float(lf) for lf, r in rates.items() if r >= 0.99]
-        out["schemes"][name] = {"success": rates, "max_lf_99pct": max(good) if good else None}
+    if not args.no_gpu:
+        import numpy as np
+        import torch
+
+        import datagen
+        import paper_2108_07232_amd as bht
+        dev = torch.device("cuda", 0)
+        keys = torch.from_numpy(datagen.unique_keys(n, args.seed).view(np.int32)).to(dev)
+        vals = torch.from_numpy(datagen.values(n, args.seed).view(np.int32)).to(dev)
+        for name, scheme, b, h, thr, lfs in sweep:
+            rates = {}
+            for lf in lfs:
+                cap = datagen.capacity_for(n, lf)
+                ok = 0
+                table = None
+                for run in range(args.runs):
+                    s = success_seed(args, run)
+                    a, c = datagen.hash_constants(s, h)
+                    if table is None:
+                        table = bht.Table(cap, b, scheme, a, c, rng_seed=datagen.rng_seed(s),
+                                          iht_threshold=thr)
+                    else:
+                        bht.bht_reseed(table.handle, bht.make_params(
+                            a, c, rng_seed=datagen.rng_seed(s), iht_threshold=thr))
+                    ok += table.build(keys, vals) == bht.BHT_OK
+                table.close()
+                rates[str(lf)] = round(ok / args.runs, 4)
+                log("success %s LF %.2f: %d/%d" % (name, lf, ok, args.runs))
+            good = [float(lf) for lf, r in rates.items() if r >= 0.99]
+            out["schemes"][name] = {"success": rates, "max_lf_99pct": max(good) if good else None}
+        del keys, vals
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = success_serial(args, sweep, n)
     line = json.dumps(out)
     print(line, flush=True)
     if args.out:
         with open(args.out, "a") as f:
             f.write(line + "\n")
+
+
+def success_seed(args, run):
+    return args.seed * 100003 + run
+
+
+_SERIAL_INPUT = {}
+
+
+def _serial_build(task):
+    """One serial build of the oracle (a worker process): status code."""
+    import datagen
+    import oracle
+    seed, log2n, scheme, b, h, thr, lf, s = task
+    n = 1 << log2n
+    if (seed, log2n) not in _SERIAL_INPUT:
+        _SERIAL_INPUT.clear()
+        _SERIAL_INPUT[(seed, log2n)] = (datagen.unique_keys(n, seed), datagen.values(n, seed))
+    keys, vals = _SERIAL_INPUT[(seed, log2n)]
+    params = oracle.params_for(scheme, n, lf, s, b=b, h=h, threshold=thr)
+    st, _, _ = oracle.build32(params, keys, vals)
+    return int(st == oracle.OK)
+
+
+def success_serial(args, sweep, n):
+    """The oracle's serial builds of the success sweep, same keys and hash
+    constants as the GPU's, spread over worker processes (one build each)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+    tasks, where = [], []
+    for name, scheme, b, h, thr, lfs in sweep:
+        for lf in lfs:
+            for run in range(args.runs):
+                tasks.append((args.seed, args.log2n, scheme, b, h, thr, lf, success_seed(args, run)))
+                where.append((name, str(lf)))
+    t0 = time.time()
+    ok = {}
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        for (name, lf), good in zip(where, ex.map(_serial_build, tasks, chunksize=4)):
+            ok.setdefault(name, {}).setdefault(lf, 0)
+            ok[name][lf] += good
+    schemes = {}
+    for name, per_lf in ok.items():
+        rates = {lf: round(c / args.runs, 4) for lf, c in per_lf.items()}
+        good = [float(lf) for lf, r in rates.items() if r >= 0.99]
+        schemes[name] = {"success": rates, "max_lf_99pct": max(good) if good else None}
+        log("serial %s: %s" % (name, rates))
+    return {"kind": "oracle", "cores": workers, "seconds": round(time.time() - t0, 1),
+            "sample": "the oracle's serial build of the same 2^%d keys with the same %d "
+                      "hash-constant sets per load factor" % (args.log2n, args.runs),
+            "schemes": schemes}
 
 
 def main():
@@ -1022,8 +1090,9 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload == "success":
-        import torch
-        torch.cuda.set_device(0)
+        if not args.no_gpu:
+            import torch
+            torch.cuda.set_device(0)
         if args.log2n == 28:
             args.log2n = 24
         run_success(args)

@@ -57,6 +57,29 @@ def test_library_hash32_equals_oracle():
         assert bht.bht_hash32(a, c, k, m) == oracle.hash32(a, c, k, m)
 
 
+def test_library_hash32_quotient_boundaries():
+    """The bucket reduction takes r mod m from a fixed-point reciprocal of m
+    (no division); a wrong quotient would first show at multiples of m.
+    With a = 1, c = 0 the residue r equals the key (k < p), so keys at
+    q m - 1, q m, q m + 1 and q m + m - 1 probe those boundaries for
+    divisors of every size, powers of two and the two sides of 2^31 among
+    them."""
+    import paper_2108_07232_amd as bht
+    P = 4294967291
+    rng = np.random.default_rng(7)
+    ms = [1, 2, 3, 5, 7, 16, 1000, 72818, 9320676, 18641352, 167772160, (1 << 30) + 3,
+          (1 << 31) - 1, 1 << 31, (1 << 31) + 1, 3000000019, 0xFFFFFFFE, 0xFFFFFFFF]
+    ms += [1 << s for s in range(1, 32)]
+    ms += [int(x) for x in rng.integers(1, 1 << 32, 40)]
+    for m in ms:
+        qmax = (P - 1) // m
+        qs = {0, 1, qmax, max(qmax - 1, 0)} | {int(x) for x in rng.integers(0, qmax + 1, 30)}
+        for q in qs:
+            for r in (q * m - 1, q * m, q * m + 1, q * m + m - 1):
+                if 0 <= r < P:
+                    assert bht.bht_hash32(1, 0, r, m) == r % m, (r, m)
+
+
 def test_library_hash64_equals_oracle():
     import paper_2108_07232_amd as bht
     Q = (1 << 61) - 1
