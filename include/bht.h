@@ -193,6 +193,23 @@ bht_status bht_build_async_in(bht_table* t, const uint32_t* d_keys, const uint32
                               uint64_t n, void* d_workspace, uint64_t workspace_bytes,
                               void* stream);
 
+/* For callers that cannot allocate device memory while they build (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): as bht_build_async_in, but the partitioned path's workspace is
+ * a fixed array inside the library (bht_build_noalloc_max_bytes() bytes,
+ * 64 MiB: about 8 M pairs), one per GPU, held until the process ends, so
+ * the call allocates nothing.  Builds the default would give the concurrent
+ * kernel need no workspace and take that kernel.  Finish with
+ * bht_build_wait.  The table's device must be current.  CAPACITY when the
+ * build needs more workspace than the array holds.  Every call on one GPU
+ * shares that GPU's array: builds through this entry point that overlap on
+ * one GPU (other streams, other threads) race and must be serialized by the
+ * caller; the array keeps the last build's contents, and each build clears
+ * what it counts with before use. */
+uint64_t bht_build_noalloc_max_bytes(void);
+bht_status bht_build_async_noalloc(bht_table* t, const uint32_t* d_keys,
+                                   const uint32_t* d_values, uint64_t n, void* stream);
+
 /* Bulk find of n queries (Section III; Section V).  d_out_values[i] is the
  * value stored with d_queries[i], or 0xFFFFFFFF when absent; d_out_found[i]
  * is 1 when present, else 0.  Asynchronous on stream; the table must be

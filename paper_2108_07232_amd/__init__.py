@@ -92,6 +92,8 @@ _SIGS = {
     "bht_build_counted": (_st, [_p, _p, _p, _u64, _p, _p]),
     "bht_build_workspace_bytes": (_u64, [_p, _u64]),
     "bht_build_async_in": (_st, [_p, _p, _p, _u64, _p, _u64, _p]),
+    "bht_build_noalloc_max_bytes": (_u64, []),
+    "bht_build_async_noalloc": (_st, [_p, _p, _p, _u64, _p]),
     "bht_build_stats": (_st, [_p, ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "bht_params_from_seed": (_st, [_u64, ctypes.c_int, _u32, ctypes.POINTER(bht_params)]),
     "bht_build_retry": (_st, [_p, _p, _p, _u64, _u64, _u32, ctypes.POINTER(_u32), _p]),
@@ -242,6 +244,22 @@ def bht_build_async_in(table, keys, values, workspace, n=None, stream=None):
     _check(_lib.bht_build_async_in(table, _dptr(keys, None, "keys"), _dptr(values, None, "values"),
                                    n, _dptr(workspace, None, "workspace"), nbytes, _stream(stream)),
            "bht_build_async_in")
+
+
+def bht_build_noalloc_max_bytes() -> int:
+    return int(_lib.bht_build_noalloc_max_bytes())
+
+
+def bht_build_async_noalloc(table, keys, values, n=None, stream=None) -> int:
+    """Enqueues a build whose workspace is the library's fixed per-GPU array
+    (no device allocation); returns the status (CAPACITY when the build
+    needs more workspace than the array holds)."""
+    n = keys.numel() if n is None else n
+    st = _lib.bht_build_async_noalloc(table, _dptr(keys, None, "keys"),
+                                      _dptr(values, None, "values"), n, _stream(stream))
+    if st not in (BHT_OK, BHT_ERR_CAPACITY):
+        _check(st, "bht_build_async_noalloc")
+    return st
 
 
 def bht_build_wait(table, stream=None) -> int:

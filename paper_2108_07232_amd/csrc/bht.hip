@@ -1040,6 +1040,71 @@ bht_status bht_build_async_in(bht_table* t, const uint32_t* d_keys, const uint32
                              workspace_bytes);
 }
 
+}  // extern "C"
+
+// Workspace of the no-allocation build: device memory of the library's code
+// object, one copy per GPU, held until the process ends.  In host code the
+// array's name stands for a host-side shadow, never for device memory: its
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr uint64_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// *out <- this device's copy of the scratch array; dev must be current.
+bht_status scratch_for(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(BHT_ERR_INVALID_ARG, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(BHT_ERR_HIP, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t bht_build_noalloc_max_bytes(void) { return kScratchBytes; }
+
+bht_status bht_build_async_noalloc(bht_table* t, const uint32_t* d_keys,
+                                   const uint32_t* d_values, uint64_t n, void* stream) {
+  if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
+  if (t->key_bits != 32) return fail(BHT_ERR_INVALID_ARG, "table holds 64-bit keys");
+  if (n > t->slots) return fail(BHT_ERR_CAPACITY, "more pairs than slots");
+  if (n && (!d_keys || !d_values)) return fail(BHT_ERR_INVALID_ARG, "null key or value pointer");
+  // the concurrent path has no workspace and allocates nothing
+  if (!use_partitioned(t, n, false)) return build32_enqueue(t, d_keys, d_values, n, nullptr, stream);
+  PartPlan P;
+  if (!part_plan(t, n, &P)) return fail(BHT_ERR_UNSUPPORTED, "table too large to partition");
+  const uint64_t need = part_layout(P, n).bytes;
+  if (need > kScratchBytes)
+    return fail(BHT_ERR_CAPACITY, "build needs " + std::to_string(need) +
+                                      " bytes of workspace; the no-allocation scratch holds " +
+                                      std::to_string(kScratchBytes));
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != t->device) return fail(BHT_ERR_INVALID_ARG, "the table's device is not current");
+  void* ws = nullptr;
+  const bht_status s = scratch_for(dev, &ws);
+  if (s != BHT_OK) return s;
+  KernelSet ks;
+  if (!pick(t, t->tile, t->find_schedule, false, &ks))
+    return fail(BHT_ERR_UNSUPPORTED, "no kernel for this bucket size and tile width");
+  t->built = false;
+  t->pending_partitioned = false;
+  return build32_partitioned(t, d_keys, d_values, n, as_stream(stream), ws, kScratchBytes);
+}
+
 bht_status bht_build_wait(bht_table* t, void* stream) {
   if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
   if (!t->pending) return t->built ? BHT_OK : fail(BHT_ERR_NOT_BUILT, "no build pending");
