@@ -35,6 +35,8 @@
 // the early-exit property), and lookups are unchanged.  Pair order within a
 // bin or digit is not preserved and need not be.
 #pragma once
+#include <type_traits>
+
 #include "bht_kernels.hpp"
 
 namespace bht {
@@ -50,7 +52,11 @@ namespace bht {
 #ifndef BHT_SCATTER_BLOCKS_PER_CU
 #define BHT_SCATTER_BLOCKS_PER_CU 1
 #endif
+#ifndef BHT_SCATTER_STAGE_DIGITS
+#define BHT_SCATTER_STAGE_DIGITS 1
+#endif
 constexpr int kScatterBlocksPerCU = BHT_SCATTER_BLOCKS_PER_CU;   // occupancy the scatter is compiled for
+constexpr bool kScatterStageDigits = BHT_SCATTER_STAGE_DIGITS != 0; // digits staged beside the pairs
 constexpr int kPartBlock = 256;                        // threads per scan block
 constexpr int kPassBlock = BHT_PASS_BLOCK;
 constexpr int kPartSub = BHT_PASS_PER * kPassBlock;   // pairs per sub-tile (4-byte words)
@@ -228,22 +234,33 @@ __device__ __forceinline__ bool hist_range(const T* __restrict__ in_k, uint64_t 
   __syncthreads();
   bool sentinel = false;
   constexpr int U = 8;
-  for (uint64_t base = begin; base < end; base += U * kPassBlock) {
+  // 32-bit offsets from the range's start (a range is one chunk, at most
+  // kPartChunkMax pairs), so the address arithmetic stays in single registers
+  const T* __restrict__ kb = in_k + begin;
+  const uint32_t len = (uint32_t)(end - begin);
+  for (uint32_t base = 0; base < len; base += U * kPassBlock) {
     T k[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      // branch-free loads: indices past the end re-read the last pair
-      const uint64_t i = base + j * kPassBlock + threadIdx.x;
-      k[j] = in_k[i < end ? i : end - 1];
+      // branch-free loads: offsets past the end re-read the last pair
+      const uint32_t o = base + j * kPassBlock + threadIdx.x;
+      k[j] = kb[o < len ? o : len - 1];
     }
+    // a full group of U pairs per thread is counted without per-pair guards,
+    // so the counting atomics issue back to back
+    auto count_group = [&](auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
 #pragma unroll
-    for (int j = 0; j < U; ++j) {
-      const uint64_t i = base + j * kPassBlock + threadIdx.x;
-      if (i < end) {
-        sentinel |= reserved_key(k[j]);
-        atomicAdd(&cnt[digit(k[j])], 1u);
+      for (int j = 0; j < U; ++j) {
+        const uint32_t o = base + j * kPassBlock + threadIdx.x;
+        if (FULL || o < len) {
+          sentinel |= reserved_key(k[j]);
+          atomicAdd(&cnt[digit(k[j])], 1u);
+        }
       }
-    }
+    };
+    if (base + U * kPassBlock <= len) count_group(std::integral_constant<bool, true>());
+    else count_group(std::integral_constant<bool, false>());
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) {
@@ -332,75 +349,114 @@ __device__ __forceinline__ void scatter_range(const T* __restrict__ in_k,
   constexpr int PER = SUB / kPassBlock;
   __shared__ T sk[SUB];
   __shared__ T sv[SUB];
+  __shared__ uint8_t sd[kScatterStageDigits ? SUB : 1];
   __shared__ uint32_t cnt[kMaxFan];
   __shared__ uint32_t start[kMaxFan];
   __shared__ uint32_t run[kMaxFan];
   __shared__ uint32_t wt[kPassBlock / 64];
+  // With at most 256 digits each staged pair's digit is kept as a byte, so
+  // the write-out needs no second hash evaluation.
+  const bool staged = kScatterStageDigits && fan <= 256;
   for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) {
     const uint32_t c = hrow[d];
     run[d] = c ? (uint32_t)atomicAdd(&cur[d], (unsigned long long)c) : 0u;
+    cnt[d] = 0;
   }
-  // Loads are branch-free (indices past the end re-read the last pair, and
+  // Loads are branch-free (offsets past the end re-read the last pair, and
   // those copies are never ranked), so the compiler can leave the next
-  // sub-tile's loads in flight while the current one is ranked.
-  const uint64_t last = end - 1;
+  // sub-tile's loads in flight while the current one is ranked.  Offsets
+  // are 32-bit, from the range's start (a range is one chunk, at most
+  // kPartChunkMax pairs), so the address arithmetic stays in single
+  // registers.
+  const T* __restrict__ kb = in_k + begin;
+  const T* __restrict__ vb = in_v + begin;
+  const uint32_t len = (uint32_t)(end - begin);
+  const uint32_t last = len - 1;
   T k[PER], v[PER];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const uint64_t i = begin + j * kPassBlock + threadIdx.x;
-    k[j] = in_k[i < end ? i : last];
-    v[j] = in_v[i < end ? i : last];
+    const uint32_t o = j * kPassBlock + threadIdx.x;
+    k[j] = kb[o < len ? o : last];
+    v[j] = vb[o < len ? o : last];
   }
-  for (uint64_t sub = begin; sub < end; sub += SUB) {
+  for (uint32_t sub = 0; sub < len; sub += SUB) {
     T nk[PER], nv[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      const uint64_t i = sub + SUB + j * kPassBlock + threadIdx.x;
-      nk[j] = in_k[i < end ? i : last];
-      nv[j] = in_v[i < end ? i : last];
+      const uint32_t o = sub + SUB + j * kPassBlock + threadIdx.x;
+      nk[j] = kb[o < len ? o : last];
+      nv[j] = vb[o < len ? o : last];
     }
-    for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) cnt[d] = 0;
+    // cnt was cleared before the loop or by the previous sub-tile, ahead of
+    // a barrier
     __syncthreads();
     // rank within the digit (< 2^14) and digit (< 2^10) share a register
     static_assert(SUB <= (1 << 22) && kMaxFan <= 1024, "rank and digit packing");
-    uint32_t rd[PER];
+    const uint32_t count = len - sub < (uint32_t)SUB ? len - sub : (uint32_t)SUB;
+    // One body, instantiated for a full sub-tile (no per-pair guards, so
+    // the compiler can issue a thread's LDS accesses back to back instead of
+    // one guarded block at a time) and for a partial one; and for digits
+    // staged in LDS or recomputed.  Both choices are uniform over the block.
+    auto body = [&](auto full_tag, auto staged_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
+      constexpr bool STAGED = decltype(staged_tag)::value;
+      uint32_t rd[PER];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const uint64_t i = sub + j * kPassBlock + threadIdx.x;
-      if (i < end) {
-        const uint32_t d = digit(k[j]);
-        rd[j] = (atomicAdd(&cnt[d], 1u) << 10) | d;
+      for (int j = 0; j < PER; ++j) {
+        const uint32_t i = j * kPassBlock + threadIdx.x;
+        if (FULL || i < count) {
+          const uint32_t d = digit(k[j]);
+          rd[j] = (atomicAdd(&cnt[d], 1u) << 10) | d;
+        }
       }
-    }
-    __syncthreads();
-    block_exclusive_scan<kPassBlock, uint32_t>(cnt, start, fan, wt);
+      __syncthreads();
+      block_exclusive_scan<kPassBlock, uint32_t>(cnt, start, fan, wt);
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const uint64_t i = sub + j * kPassBlock + threadIdx.x;
-      if (i < end) {
-        const uint32_t pos = start[rd[j] & 1023u] + (rd[j] >> 10);
-        sk[pos] = k[j];
-        sv[pos] = v[j];
+      for (int j = 0; j < PER; ++j) {
+        const uint32_t i = j * kPassBlock + threadIdx.x;
+        if (FULL || i < count) {
+          const uint32_t d = rd[j] & 1023u;
+          const uint32_t pos = start[d] + (rd[j] >> 10);
+          sk[pos] = k[j];
+          sv[pos] = v[j];
+          if (STAGED) sd[pos] = (uint8_t)d;
+        }
       }
-    }
-    __syncthreads();
-    const uint32_t count = end - sub < (uint64_t)SUB ? (uint32_t)(end - sub) : SUB;
-    // fixed trip count (no inner loop), so the prefetched loads stay in
-    // flight across the stores
+      __syncthreads();
+      // start[d] becomes the offset from a staged position to its output
+      // position; the digit's run advances and its count clears for the
+      // next sub-tile (whose ranking follows this write-out without a
+      // barrier)
+      for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) {
+        const uint32_t c = cnt[d];
+        start[d] = run[d] - start[d];
+        run[d] += c;
+        cnt[d] = 0;
+      }
+      __syncthreads();
+      // fixed trip count (no inner loop), so the prefetched loads stay in
+      // flight across the stores
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const uint32_t i = j * kPassBlock + threadIdx.x;
-      if (i < count) {
-        const T key = sk[i];
-        const uint32_t d = digit(key);                        // recomputed, not stored
-        const uint32_t dst = run[d] + (i - start[d]);
-        out_k[dst] = key;
-        out_v[dst] = sv[i];
+      for (int j = 0; j < PER; ++j) {
+        const uint32_t i = j * kPassBlock + threadIdx.x;
+        if (FULL || i < count) {
+          const T key = sk[i];
+          const uint32_t d = STAGED ? (uint32_t)sd[i] : digit(key);
+          const uint32_t dst = start[d] + i;
+          out_k[dst] = key;
+          out_v[dst] = sv[i];
+        }
       }
+    };
+    using yes = std::integral_constant<bool, true>;
+    using no = std::integral_constant<bool, false>;
+    if (staged) {
+      if (count == (uint32_t)SUB) body(yes(), yes());
+      else body(no(), yes());
+    } else {
+      if (count == (uint32_t)SUB) body(yes(), no());
+      else body(no(), no());
     }
-    __syncthreads();
-    for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) run[d] += cnt[d];
-    // the next sub-tile's first barrier orders these updates before use
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       k[j] = nk[j];
@@ -458,7 +514,8 @@ __device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
   constexpr int S = bin_slots<B>();
   constexpr int RMAX = S / B;                    // buckets per bin, at most
   __shared__ u64x2 tbl2[S / 2];
-  __shared__ uint32_t load[RMAX];
+  __shared__ uint32_t load[RMAX + 1];            // [RMAX]: target of lanes without a pair
+  __shared__ unsigned long long spill;           // target of the stores of those lanes
   __shared__ uint32_t ovf;
   unsigned long long* tbl = reinterpret_cast<unsigned long long*>(tbl2);
   const u64x2 e2 = {kEmptyPair, kEmptyPair};
@@ -468,31 +525,39 @@ __device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
   uint32_t rng = rng_seed ^ (salt * 0x9E3779B9u) ^ (threadIdx.x * 0x85EBCA6Bu);
   if (rng == 0) rng = 0x2545F491u;
   uint32_t flags = 0;
+  // the bin's pairs, addressed by 32-bit offsets (the partitioned path
+  // takes fewer than 2^32 pairs)
+  uint32_t* __restrict__ kb = keys + s0;
+  uint32_t* __restrict__ vb = vals + s0;
+  const uint32_t n_bin = (uint32_t)len;
   __syncthreads();
-  for (uint64_t r0 = 0; r0 < len; r0 += (uint64_t)kBinBlock * kBinPer) {
+  for (uint32_t r0 = 0; r0 < n_bin; r0 += kBinBlock * kBinPer) {
     uint32_t k[kBinPer], v[kBinPer], full[kBinPer];
 #pragma unroll
     for (int j = 0; j < kBinPer; ++j) {
-      // branch-free loads: indices past the end re-read the bin's last pair
-      const uint64_t i = r0 + j * kBinBlock + threadIdx.x;
-      k[j] = keys[s0 + (i < len ? i : len - 1)];
-      v[j] = vals[s0 + (i < len ? i : len - 1)];
+      // branch-free loads: offsets past the end re-read the bin's last pair
+      const uint32_t i = r0 + j * kBinBlock + threadIdx.x;
+      k[j] = kb[i < n_bin ? i : n_bin - 1];
+      v[j] = vb[i < n_bin ? i : n_bin - 1];
     }
 #pragma unroll
     for (int j = 0; j < kBinPer; ++j) {
       full[j] = ~0u;
-      const uint64_t i = r0 + j * kBinBlock + threadIdx.x;
-      if (i < len) {
-        // lb < nb by construction of the partition
-        const uint32_t lb = hash32(H, 0, k[j]) - (uint32_t)first;
-        if (lb >= nb) {
-          flags |= kFlagFailed;
-        } else {
-          const uint32_t s = atomicAdd(&load[lb], 1u);
-          if (s < cap) tbl[lb * B + s] = ((unsigned long long)v[j] << 32) | k[j];
-          else full[j] = lb;
-        }
-      }
+      const uint32_t i = r0 + j * kBinBlock + threadIdx.x;
+      // No branch per pair: a lane without a pair (past the bin's end)
+      // counts on a spare counter and stores to a spare word, so the
+      // claims of a thread's pairs issue back to back.  lb < nb by
+      // construction of the partition; otherwise the build fails.
+      const uint32_t lb = hash32(H, 0, k[j]) - (uint32_t)first;
+      const bool valid = i < n_bin;
+      const bool inside = lb < nb;
+      if (valid && !inside) flags |= kFlagFailed;
+      const bool claim = valid && inside;
+      const uint32_t s = atomicAdd(&load[claim ? lb : (uint32_t)RMAX], 1u);
+      const bool placed = claim && s < cap;
+      unsigned long long* dst = placed ? &tbl[lb * B + s] : &spill;
+      *dst = ((unsigned long long)v[j] << 32) | k[j];
+      if (claim && !placed) full[j] = lb;
     }
     // Every claimed slot is written, and every pair of this round has been
     // read: evicted pairs go to positions below the running eviction count.
@@ -520,8 +585,8 @@ __device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
 #pragma unroll
     for (int j = 0; j < kBinPer; ++j) {
       if (full[j] != ~0u) {
-        keys[s0 + full[j]] = k[j];
-        vals[s0 + full[j]] = v[j];
+        kb[full[j]] = k[j];
+        vb[full[j]] = v[j];
       }
     }
   }
