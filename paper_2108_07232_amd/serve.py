@@ -3,9 +3,11 @@
 Requests arrive over time (an open-loop arrival schedule): a *build*
 creates a new table from caller-supplied device keys and values, a *lookup*
 answers a query batch against a resident table.  The loop admits requests
-as they arrive, keeps tables resident in HBM under a byte budget (least
-recently used tables are evicted when a build needs room; a table with
-lookups waiting or in flight is never evicted), and launches every lookup
+as they arrive, keeps tables resident in HBM under a byte budget that
+covers the tables and the per-stream build workspaces (least recently used
+tables are evicted when a build needs room; a table with lookups waiting or
+in flight is never evicted; request keys, queries and outputs are the
+caller's and outside the budget), and launches every lookup
 that is ready, from any number of tables, as one coalesced query launch on
 a free stream, so new work is admitted while earlier launches still run.
 Completion is observed with events; a request's latency runs from its
@@ -78,9 +80,11 @@ class Server:
             slot.done_event = torch.cuda.Event()
         # one build workspace per build stream (reused: a slot runs one build
         # at a time), so builds never allocate in the loop; grown on demand
+        self.ws_bytes = 0                            # build workspaces, inside the budget
         for slot in self.build_slots:
             if workspace_bytes:
                 slot.workspace = torch.empty(workspace_bytes, dtype=torch.uint8, device="cuda")
+                self.ws_bytes += workspace_bytes
         self.building = set()                        # ids with a build waiting or running
 
     def close(self):
@@ -122,7 +126,13 @@ class Server:
             bht.bht_build_async(table.handle, keys, vals, stream=slot.stream)
             return
         if slot.workspace is None or slot.workspace.numel() < need:
+            # a grown workspace counts against the budget like a table
+            old = 0 if slot.workspace is None else slot.workspace.numel()
+            slot.workspace = None
+            self.ws_bytes -= old
+            self._make_room(need)
             slot.workspace = self.torch.empty(need, dtype=self.torch.uint8, device="cuda")
+            self.ws_bytes += need
         bht.bht_build_async_in(table.handle, keys, vals, slot.workspace, stream=slot.stream)
 
     # ------------------------------------------------------------- tables
@@ -134,7 +144,7 @@ class Server:
         self.bytes += table.info[3]
 
     def _make_room(self, need: int) -> bool:
-        while self.bytes + need > self.budget:
+        while self.bytes + self.ws_bytes + need > self.budget:
             victim = next((tid for tid in self.tables if self.pins[tid] == 0 and tid in self.ready),
                           None)
             if victim is None:
