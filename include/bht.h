@@ -347,12 +347,18 @@ bht_status bht_device_slots(const bht_table* t, void** d_slots);
  * (bytes long), line_bytes/16 lanes x 16 bytes per block, no table logic;
  * with 128 it is the access pattern of one bucket probe.  bht_diag_cas issues
  * n_ops random 8-byte compare-and-swaps on d_buf that never change it (the
- * new value equals the expected one).  d_sink is a device uint64 the
- * kernels may write.  Both are asynchronous on stream. */
+ * new value equals the expected one).  bht_diag_stream reads the first
+ * bytes of d_src in order (16-byte words, bytes rounded down to a multiple
+ * of 16) and, when d_dst is not NULL, writes them to d_dst (a device copy;
+ * the ranges must not overlap), else only reads them: the streaming
+ * ceilings.  Both buffers 16-byte aligned.  d_sink is a device uint64 the
+ * kernels may write.  All are asynchronous on stream. */
 bht_status bht_diag_gather(const void* d_buf, uint64_t bytes, uint64_t n_reads, uint32_t line_bytes,
                            uint64_t seed, uint64_t* d_sink, void* stream);
 bht_status bht_diag_cas(void* d_buf, uint64_t bytes, uint64_t n_ops, uint64_t seed,
                         uint64_t* d_sink, void* stream);
+bht_status bht_diag_stream(const void* d_src, void* d_dst, uint64_t bytes, uint64_t* d_sink,
+                           void* stream);
 
 /* Batched mode (not in the paper): many bucketed cuckoo tables of uneven
  * sizes built and then queried together.  Every table of a batch is a

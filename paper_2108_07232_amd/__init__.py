@@ -111,6 +111,7 @@ _SIGS = {
     "bht_device_slots": (_st, [_p, _pp]),
     "bht_diag_gather": (_st, [_p, _u64, _u64, _u32, _u64, _p, _p]),
     "bht_diag_cas": (_st, [_p, _u64, _u64, _u64, _p, _p]),
+    "bht_diag_stream": (_st, [_p, _p, _u64, _p, _p]),
     "bht_hash32": (_u64, [_u64, _u64, _u32, _u64]),
     "bht_hash64": (_u64, [_u64, _u64, _u64, _u64]),
     "bht_batch_create": (_st, [ctypes.POINTER(bht_batch_entry), _u32, _u32, _pp]),
@@ -421,6 +422,14 @@ def bht_diag_gather(d_buf: int, nbytes: int, n_reads: int, line_bytes: int, seed
 def bht_diag_cas(d_buf: int, nbytes: int, n_ops: int, seed, sink, stream=None):
     _check(_lib.bht_diag_cas(ctypes.c_void_p(d_buf), nbytes, n_ops, seed,
                              _dptr(sink, None, "sink"), _stream(stream)), "bht_diag_cas")
+
+
+def bht_diag_stream(d_src: int, d_dst, nbytes: int, sink, stream=None):
+    """Streaming ceiling: copy nbytes from d_src to d_dst, or read them when
+    d_dst is None (raw device addresses)."""
+    _check(_lib.bht_diag_stream(ctypes.c_void_p(d_src),
+                                None if d_dst is None else ctypes.c_void_p(d_dst), nbytes,
+                                _dptr(sink, None, "sink"), _stream(stream)), "bht_diag_stream")
 
 
 def bht_hash32(a: int, b: int, k: int, m: int) -> int:

@@ -117,6 +117,20 @@ bht_status hip_fail(hipError_t e, const char* what) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Pairs per lane (at least) of the builds whose placements compare bucket
+// loads, which bounds the placements in flight.
+#ifndef BHT_LB_PAIRS_PER_LANE
+#define BHT_LB_PAIRS_PER_LANE 32
+#endif
+constexpr uint64_t kLbPairsPerLane = BHT_LB_PAIRS_PER_LANE;
+
+// Secondary buckets per lane of the partitioned iceberg build's overflow
+// phase (bounds its secondary choices in flight; 1 = the whole device).
+#ifndef BHT_ICEBERG_OVF_SPREAD
+#define BHT_ICEBERG_OVF_SPREAD 1
+#endif
+constexpr uint64_t kIcebergOverflowSpread = BHT_ICEBERG_OVF_SPREAD;
+
 // Blocks to launch: enough to give every lane an item, capped at what the
 // device keeps resident at once (the kernels loop over their share).
 // items_per_lane > 0 asks for at least ceil(items / (256 * items_per_lane))
@@ -714,14 +728,14 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
     ia.g.threshold = t->params.iht_threshold;
     ia.M = M;
     ia.nbins = P.nbins;
-    // Secondary choices are made on loads read before the CAS; with many
-    // pairs in flight they choose from the same stale loads and pile into
-    // the same buckets, and near the load limit builds fail that a serial
-    // insertion in the same order completes.  One lane per 32 secondary
-    // buckets keeps the placements in flight to ~3% of those buckets (at
-    // 2^27 pairs, LF 0.86: 6 of 6 builds succeed, 1 of 6 with a full device).
+    // Secondary choices are made on device-scope reads and made again when
+    // a concurrent placement takes the chosen slot, so they follow current
+    // loads with the whole device in flight (at 2^27 pairs the highest load
+    // factor reached is 0.86 at any spread from 1 to 32 secondary buckets
+    // per lane; with reads that could be stale a full device failed 5 of 6
+    // builds at 0.86 and needed a spread of 32).
     const uint64_t sec_buckets = t->params.iht_secondary_b ? t->params.iht_secondary_m : t->m;
-    const uint64_t lanes = std::max<uint64_t>(sec_buckets / 32, 64);
+    const uint64_t lanes = std::max<uint64_t>(sec_buckets / kIcebergOverflowSpread, 64);
     const int ig = grid_for(K.overflow, lanes, t->grid_blocks);
     reinterpret_cast<void (*)(IcebergOverflowArgs)>(const_cast<void*>(K.overflow))
         <<<ig, kBlock, 0, st>>>(ia);
@@ -773,7 +787,8 @@ bht_status build32_enqueue(bht_table* t, const uint32_t* keys, const uint32_t* v
     // flight at once those loads would all be stale.  Giving each lane at
     // least 32 pairs keeps the pairs in flight under ~3% of the table, so
     // placement matches the serial rule; large tables still fill the device.
-    const uint64_t grid_items = ks.kind == Kind::Cuckoo ? n : (n + 31) / 32;
+    const uint64_t grid_items =
+        ks.kind == Kind::Cuckoo ? n : (n + kLbPairsPerLane - 1) / kLbPairsPerLane;
     const int grid = grid_for(ks.build, grid_items, t->grid_blocks);
     if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
     if (ks.kind == Kind::Cuckoo || ks.kind == Kind::LoadBalanced) {
@@ -1442,6 +1457,26 @@ bht_status bht_diag_gather(const void* d_buf, uint64_t bytes, uint64_t n_reads, 
   BHT_GATHER(128)
   BHT_GATHER(256)
 #undef BHT_GATHER
+  HIP_TRY(hipGetLastError());
+  return BHT_OK;
+}
+
+bht_status bht_diag_stream(const void* d_src, void* d_dst, uint64_t bytes, uint64_t* d_sink,
+                           void* stream) {
+  if (!d_src || !d_sink || bytes < 16) return fail(BHT_ERR_INVALID_ARG, "bad buffer");
+  if ((reinterpret_cast<uintptr_t>(d_src) | reinterpret_cast<uintptr_t>(d_dst)) & 15)
+    return fail(BHT_ERR_INVALID_ARG, "buffers must be 16-byte aligned");
+  const uint64_t n16 = bytes / 16;
+  const auto* src = static_cast<const u64x2*>(d_src);
+  auto* dst = static_cast<u64x2*>(d_dst);
+  auto sink = reinterpret_cast<unsigned long long*>(d_sink);
+  hipStream_t st = as_stream(stream);
+  const uint64_t blocks = (n16 + kStreamChunk - 1) / kStreamChunk;
+  if (blocks > 0x7FFFFFFFull) return fail(BHT_ERR_INVALID_ARG, "buffer too large");
+  if (dst)
+    diag_stream_kernel<true><<<(unsigned)blocks, kBlock, 0, st>>>(src, dst, n16, sink);
+  else
+    diag_stream_kernel<false><<<(unsigned)blocks, kBlock, 0, st>>>(src, nullptr, n16, sink);
   HIP_TRY(hipGetLastError());
   return BHT_OK;
 }

@@ -55,4 +55,38 @@ __global__ __launch_bounds__(kBlock) void diag_cas_kernel(uint64_t* __restrict__
   if (acc == 0x9E3779B97F4A7C15ull) atomicAdd(sink, 1ull);
 }
 
+// Streaming ceiling: reads n16 16-byte words of src in order and, with
+// WRITE, writes them to dst (a device copy); without, folds them into one
+// value (a read-only pass).  Each block streams one contiguous 64 KB
+// chunk, four words per lane in flight per step (on this part contiguous
+// per-block chunks stream faster than a grid-wide stride).  The streaming
+// phases of the partitioned build are priced against these.
+constexpr uint64_t kStreamChunk = 4096;          // 16-byte words per block
+template <bool WRITE>
+__global__ __launch_bounds__(kBlock) void diag_stream_kernel(const u64x2* __restrict__ src,
+                                                            u64x2* __restrict__ dst, uint64_t n16,
+                                                            unsigned long long* __restrict__ sink) {
+  constexpr int U = 4;
+  const uint64_t b0 = (uint64_t)blockIdx.x * kStreamChunk;
+  const uint64_t b1 = b0 + kStreamChunk < n16 ? b0 + kStreamChunk : n16;
+  uint64_t acc = 0;
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += (uint64_t)kBlock * U) {
+    u64x2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t idx = i + (uint64_t)u * kBlock;
+      if (idx < b1) v[u] = src[idx];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t idx = i + (uint64_t)u * kBlock;
+      if (idx < b1) {
+        if (WRITE) dst[idx] = v[u];
+        else acc ^= v[u].x ^ v[u].y;
+      }
+    }
+  }
+  if (!WRITE && acc == 0x9E3779B97F4A7C15ull) atomicAdd(sink, 1ull);
+}
+
 }  // namespace bht

@@ -103,14 +103,18 @@ struct Walk {
 
 enum : uint32_t { kP2Read = 0, kP2Walk1 = 1, kP2Walk2 = 2 };
 
-#ifndef BHT_P2_FRESH
-#define BHT_P2_FRESH 1
+// Placements that compare bucket loads (power of two, iceberg secondaries)
+// read the candidates with device-scope loads, and a pair whose CAS loses
+// its slot to a concurrent placement reads both candidates again and
+// chooses again, so that a choice is made on current loads.
+#ifndef BHT_CHOICE_FRESH
+#define BHT_CHOICE_FRESH 1
 #endif
-constexpr bool kP2Fresh = BHT_P2_FRESH != 0;   // power-of-two reads at device scope
-#ifndef BHT_P2_REDECIDE
-#define BHT_P2_REDECIDE 1
+constexpr bool kChoiceFresh = BHT_CHOICE_FRESH != 0;
+#ifndef BHT_CHOICE_REDECIDE
+#define BHT_CHOICE_REDECIDE 1
 #endif
-constexpr bool kP2Redecide = BHT_P2_REDECIDE != 0;  // a lost CAS re-reads both buckets
+constexpr bool kChoiceRedecide = BHT_CHOICE_REDECIDE != 0;
 
 // Power-of-two-choices insertion: read H0 and H1, claim a slot in the less
 // loaded bucket (ties to H0); if its walk runs out, the other bucket; if
@@ -156,9 +160,9 @@ __global__ __launch_bounds__(kBlock) void p2_build_kernel(SchemeArgs32 g) {
     const uint64_t rd = ballot(active && phase == kP2Read);
     if (rd) {
       Part<Slice<B, W>::S> d[W];
-      tile_read_any<B, W, kP2Fresh>(g.slots, b0, rd, tb, lt, d);
+      tile_read_any<B, W, kChoiceFresh>(g.slots, b0, rd, tb, lt, d);
       const uint32_t l0 = tile_load_any<B, W>(d, tb, lt);
-      tile_read_any<B, W, kP2Fresh>(g.slots, b1, rd, tb, lt, d);
+      tile_read_any<B, W, kChoiceFresh>(g.slots, b1, rd, tb, lt, d);
       const uint32_t l1 = tile_load_any<B, W>(d, tb, lt);
       if (active && phase == kP2Read) {
         if (COUNT) probes += 2;
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void p2_build_kernel(SchemeArgs32 g) {
       const uint64_t pair = ((uint64_t)val << 32) | key;
       if (w.slot < w.limit && cas64(g.slots + w.first + w.slot, kEmptyPair, pair) == kEmptyPair) {
         active = false;
-      } else if (kP2Redecide) {
+      } else if (kChoiceRedecide) {
         // another placement took the slot since the read: read both
         // buckets again and choose again (each retry follows a placement
         // into one of them, so a pair retries at most 2B times)
@@ -427,9 +431,9 @@ __device__ __forceinline__ uint32_t iceberg_build_range(const SchemeArgs32& g, R
     const uint64_t rs = ballot(active && phase == kIcReadS);
     if (rs) {
       Part<Slice<BS2, W>::S> d[W];
-      tile_read_any<BS2, W>(sec, s0, rs, tb, lt, d);
+      tile_read_any<BS2, W, kChoiceFresh>(sec, s0, rs, tb, lt, d);
       const uint32_t l0 = tile_load_any<BS2, W>(d, tb, lt);
-      tile_read_any<BS2, W>(sec, s1, rs, tb, lt, d);
+      tile_read_any<BS2, W, kChoiceFresh>(sec, s1, rs, tb, lt, d);
       const uint32_t l1 = tile_load_any<BS2, W>(d, tb, lt);
       if (active && phase == kIcReadS) {
         if (COUNT) probes += 2;
@@ -450,6 +454,11 @@ __device__ __forceinline__ uint32_t iceberg_build_range(const SchemeArgs32& g, R
       uint64_t* const base = w.secondary ? sec : g.slots;
       if (w.slot < w.limit && cas64(base + w.first + w.slot, kEmptyPair, pair) == kEmptyPair) {
         active = false;
+      } else if (kChoiceRedecide && (phase == kIcWalkS1 || phase == kIcWalkS2)) {
+        // a concurrent placement took the slot: read both secondaries again
+        // and choose again (bounded: each retry follows a placement into one
+        // of them)
+        phase = kIcReadS;
       } else if (w.slot + 1 < w.limit) {
         ++w.slot;
       } else if (phase == kIcWalkP) {
