@@ -42,7 +42,7 @@ def parse():
                          "at most 16)")
     ap.add_argument("--workload", default="bcht",
                     choices=["bcht", "lfsweep", "schemes", "iceberg", "latency", "batched", "serve",
-                             "success"],
+                             "success", "ceilings"],
                     help="bcht: the headline BCHT workload; schemes: the comparison of "
                          "BCHT, BP2HT, two-level iceberg, 1CHT and 64-bit BCHT")
     ap.add_argument("--only", default=None,
@@ -114,7 +114,8 @@ def partition_passes(m, b):
 def measure_ceilings(bht, table, torch, stream):
     """Random-access ceilings on the table's own slot array (2.39 GB at the
     default size): aligned random block reads of 32..256 bytes and slot-size
-    compare-and-swaps that never change memory."""
+    compare-and-swaps that never change memory; then the streaming ceilings
+    (a read-only pass, a device copy), which overwrite the slot array."""
     slots = bht.bht_device_slots(table.handle)
     _, _, _, nbytes = table.info
     sink = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -138,6 +139,19 @@ def measure_ceilings(bht, table, torch, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     out["cas_gops_s"] = round(ops / e0.elapsed_time(e1) / 1e6, 2)
+    # streaming ceilings on the same buffer: a read-only pass over all of it
+    # and a copy of its first half onto its second half (the table's
+    # contents are rebuilt afterwards)
+    half = (nbytes // 2) & ~255
+    for name, dst, nb, moved in (("stream_read", None, nbytes & ~15, nbytes & ~15),
+                                 ("stream_copy", slots + half, half, 2 * half)):
+        bht.bht_diag_stream(slots, dst, nb, sink, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        bht.bht_diag_stream(slots, dst, nb, sink, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name + "_gbs"] = round(moved / e0.elapsed_time(e1) / 1e6, 1)
     return out
 
 
@@ -679,13 +693,14 @@ def run_serve(args, rates=None, emit=True):
 
 
 SUCCESS_SWEEP = [
-    # name, scheme, slots per bucket, hashes, iceberg threshold, load factors
-    ("bcht_b16", "bcht", 16, 3, 0, (0.95, 0.96, 0.97, 0.98, 0.99)),
-    ("bp2ht_b32", "bp2ht", 32, 2, 0, (0.88, 0.89, 0.90, 0.91, 0.92)),
-    ("iht_b32_t80", "iht", 32, 3, 25, (0.88, 0.89, 0.90, 0.91, 0.92)),
-    ("cht1_h4", "cht1", 1, 4, 0, (0.85, 0.86, 0.87, 0.88, 0.89)),
-    ("bcht_lb_b16", "bcht_lb", 16, 3, 0, (0.97, 0.98, 0.99, 0.995, 1.0)),
-    ("bcht_lb_b16_h2", "bcht_lb", 16, 2, 0, (0.95, 0.96, 0.97, 0.98, 0.99)),
+    # name, scheme, slots per bucket, hashes, iceberg threshold, eviction cap, load factors
+    ("bcht_b16", "bcht", 16, 3, 0, 128, (0.95, 0.96, 0.97, 0.98, 0.99)),
+    ("bp2ht_b32", "bp2ht", 32, 2, 0, 128, (0.88, 0.89, 0.90, 0.91, 0.92)),
+    ("iht_b32_t80", "iht", 32, 3, 25, 128, (0.88, 0.89, 0.90, 0.91, 0.92)),
+    ("cht1_h4", "cht1", 1, 4, 0, 128, (0.85, 0.86, 0.87, 0.88, 0.89)),
+    ("cht1_h4_cap1024", "cht1", 1, 4, 0, 1024, (0.85, 0.86, 0.87, 0.88, 0.89)),
+    ("bcht_lb_b16", "bcht_lb", 16, 3, 0, 128, (0.97, 0.98, 0.99, 0.995, 1.0)),
+    ("bcht_lb_b16_h2", "bcht_lb", 16, 2, 0, 128, (0.95, 0.96, 0.97, 0.98, 0.99)),
 ]
 
 
@@ -980,6 +995,51 @@ def run_latency(args):
             f.write(line + "\n")
 
 
+def run_ceilings(args):
+    """Ceilings of the memory system on one 3 GiB device buffer (no table
+    logic): random 128-byte reads and random 8-byte compare-and-swaps
+    confined to regions of 3 GiB down to 1 MiB (what locality buys each),
+    and the streaming read and copy of the whole buffer."""
+    import torch
+
+    import paper_2108_07232_amd as bht
+    stream = torch.cuda.current_stream()
+    buf = torch.full((3 << 27,), -1, dtype=torch.int64, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ptr, total = buf.data_ptr(), buf.numel() * 8
+
+    def timed(fn):
+        fn(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(2)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    ops = 1 << 26
+    regions = {}
+    for mib in (3072, 1024, 256, 64, 16, 4, 1):
+        nb = mib << 20
+        g = timed(lambda s: bht.bht_diag_gather(ptr, nb, ops, 128, s, sink, stream=stream))
+        c = timed(lambda s: bht.bht_diag_cas(ptr, nb, ops, s, sink, stream=stream))
+        regions[str(mib)] = {"gather128_gacc_s": round(ops / g / 1e6, 2),
+                             "cas_gops_s": round(ops / c / 1e6, 2)}
+        log("region %d MiB: %s" % (mib, regions[str(mib)]))
+    half = total // 2
+    rd = timed(lambda s: bht.bht_diag_stream(ptr, None, total, sink, stream=stream))
+    cp = timed(lambda s: bht.bht_diag_stream(ptr, ptr + half, half, sink, stream=stream))
+    out = {"workload": "ceilings", "buffer_bytes": total, "random_ops": ops,
+           "regions_mib": regions,
+           "stream_read_gbs": round(total / rd / 1e6, 1),
+           "stream_copy_gbs": round(2 * half / cp / 1e6, 1)}
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "a") as f:
+            f.write(line + "\n")
+
+
 def run_success(args):
     """Build success rate (Section VII-D): the same keys built with `runs`
     different hash-constant sets per load factor; reports the fraction that
@@ -1000,7 +1060,7 @@ def run_success(args):
         dev = torch.device("cuda", 0)
         keys = torch.from_numpy(datagen.unique_keys(n, args.seed).view(np.int32)).to(dev)
         vals = torch.from_numpy(datagen.values(n, args.seed).view(np.int32)).to(dev)
-        for name, scheme, b, h, thr, lfs in sweep:
+        for name, scheme, b, h, thr, cap_chain, lfs in sweep:
             rates = {}
             for lf in lfs:
                 cap = datagen.capacity_for(n, lf)
@@ -1011,10 +1071,11 @@ def run_success(args):
                     a, c = datagen.hash_constants(s, h)
                     if table is None:
                         table = bht.Table(cap, b, scheme, a, c, rng_seed=datagen.rng_seed(s),
-                                          iht_threshold=thr)
+                                          iht_threshold=thr, max_chain=cap_chain)
                     else:
                         bht.bht_reseed(table.handle, bht.make_params(
-                            a, c, rng_seed=datagen.rng_seed(s), iht_threshold=thr))
+                            a, c, rng_seed=datagen.rng_seed(s), iht_threshold=thr,
+                            max_chain=cap_chain))
                     ok += table.build(keys, vals) == bht.BHT_OK
                 table.close()
                 rates[str(lf)] = round(ok / args.runs, 4)
@@ -1042,13 +1103,13 @@ def _serial_build(task):
     """One serial build of the oracle (a worker process): status code."""
     import datagen
     import oracle
-    seed, log2n, scheme, b, h, thr, lf, s = task
+    seed, log2n, scheme, b, h, thr, cap_chain, lf, s = task
     n = 1 << log2n
     if (seed, log2n) not in _SERIAL_INPUT:
         _SERIAL_INPUT.clear()
         _SERIAL_INPUT[(seed, log2n)] = (datagen.unique_keys(n, seed), datagen.values(n, seed))
     keys, vals = _SERIAL_INPUT[(seed, log2n)]
-    params = oracle.params_for(scheme, n, lf, s, b=b, h=h, threshold=thr)
+    params = oracle.params_for(scheme, n, lf, s, b=b, h=h, threshold=thr, max_chain=cap_chain)
     st, _, _ = oracle.build32(params, keys, vals)
     return int(st == oracle.OK)
 
@@ -1060,10 +1121,11 @@ def success_serial(args, sweep, n):
     import multiprocessing as mp
     workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
     tasks, where = [], []
-    for name, scheme, b, h, thr, lfs in sweep:
+    for name, scheme, b, h, thr, cap_chain, lfs in sweep:
         for lf in lfs:
             for run in range(args.runs):
-                tasks.append((args.seed, args.log2n, scheme, b, h, thr, lf, success_seed(args, run)))
+                tasks.append((args.seed, args.log2n, scheme, b, h, thr, cap_chain, lf,
+                              success_seed(args, run)))
                 where.append((name, str(lf)))
     t0 = time.time()
     ok = {}
@@ -1096,6 +1158,11 @@ def main():
         if args.log2n == 28:
             args.log2n = 24
         run_success(args)
+        return
+    if args.workload == "ceilings":
+        import torch
+        torch.cuda.set_device(0)
+        run_ceilings(args)
         return
     if args.workload == "latency":
         import torch
