@@ -98,11 +98,11 @@ uint64_t dg_feistel64(uint64_t x, uint64_t k0, uint64_t k1, uint64_t k2, uint64_
   return feistel_bits(x, rk, 32);
 }
 
-/* Distinct uint64 keys below 2^64 - 2 (the two largest values are reserved
- * markers of 64-bit tables): images cycle-walked out of the reserved pair. */
+/* Distinct uniform uint64 keys other than the all-ones empty-key sentinel:
+ * images cycle-walked out of that one value. */
 static inline uint64_t key64(uint64_t j, const uint64_t rk[4]) {
   uint64_t y = feistel_bits(j, rk, 32);
-  while (y >= 0xFFFFFFFFFFFFFFFEULL) y = feistel_bits(y, rk, 32);
+  while (y == 0xFFFFFFFFFFFFFFFFULL) y = feistel_bits(y, rk, 32);
   return y;
 }
 
