@@ -128,7 +128,11 @@ bht_status bht_reseed(bht_table* t, const bht_params* params);
  * uint32.  Resets every slot to empty and inserts all pairs with the
  * scheme's algorithm (Section III; Section V).  Waits for the stream to read
  * the device status, so the return value reports BUILD_FAILED or
- * SENTINEL_KEY.  n = 0 is valid; n above the slot count is CAPACITY. */
+ * SENTINEL_KEY.  n = 0 is valid; n above the slot count is CAPACITY.
+ * Placements that compare bucket loads (BP2HT, IHT secondaries) read the
+ * candidates with device-scope loads and, when a concurrent placement takes
+ * the chosen slot first, read both again and choose again; those re-reads
+ * count as bucket reads in bht_build_counted. */
 bht_status bht_build(bht_table* t, const uint32_t* d_keys, const uint32_t* d_values,
                      uint64_t n, void* stream);
 

@@ -390,12 +390,16 @@ Hash32 secondary_hash(const bht_table* t) {
 // Smallest build that takes the partitioned path by default: below it the
 // fixed cost of its eight launches outweighs the saved atomics.
 constexpr uint64_t kPartMinKeys = 1ull << 18;
-// The same for two-level iceberg tables, whose overflow phase runs with
-// limited concurrency (see build32_partitioned): below about 2^25 pairs
-// the concurrent build is faster.  One-level iceberg tables take the
-// partitioned path only when asked: near their load limit it fails more
-// often than the concurrent build.
-constexpr uint64_t kIcebergPartMinKeys = 1ull << 26;
+// The same for two-level iceberg tables (at LF 0.85 the partitioned build
+// is 1.7-2.2x the concurrent one from 2^18 to 2^26 pairs, every build of
+// 12 succeeding on both).  One-level iceberg tables take the partitioned
+// path only when asked: near their load limit (t = 13, LF 0.85) it
+// succeeded for 10, 8 and 3 of 12 constant sets at 2^20, 2^22 and 2^24
+// pairs, where the concurrent build succeeded for all.
+#ifndef BHT_ICEBERG_PART_MIN_LOG2
+#define BHT_ICEBERG_PART_MIN_LOG2 18
+#endif
+constexpr uint64_t kIcebergPartMinKeys = 1ull << BHT_ICEBERG_PART_MIN_LOG2;
 
 struct PartKernels {
   const void* place;

@@ -298,8 +298,8 @@ def test_iceberg_partitioned_build(b, b2, thr, lf, n):
 
 def test_iceberg_build_modes_agree():
     """Concurrent and partitioned iceberg builds of the same input give valid
-    layouts and identical lookups; below 2^26 pairs the default takes the
-    concurrent path."""
+    layouts and identical lookups; from 2^18 pairs the default takes the
+    partitioned path for a two-level table."""
     import torch
     B = bht()
     n = 1 << 19
@@ -313,7 +313,7 @@ def test_iceberg_build_modes_agree():
                     build_mode=mode)
         assert t.build(dev(keys), dev(vals)) == B.BHT_OK
         assert oracle.check32(p, t.download(), keys, vals)[0] == 0
-        assert B.bht_build_stats(t.handle)[0] == (mode == "partitioned")
+        assert B.bht_build_stats(t.handle)[0] == (mode != "concurrent")
         v, f = t.find(dev(q))
         torch.cuda.synchronize()
         results.append((host_u32(v), host_u8(f)))
