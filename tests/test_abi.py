@@ -80,6 +80,18 @@ def test_library_hash32_quotient_boundaries():
                     assert bht.bht_hash32(1, 0, r, m) == r % m, (r, m)
 
 
+def test_diagnostics_reject_bad_buffers_before_touching_the_device():
+    import paper_2108_07232_amd as bht
+    lib = bht._lib
+    sink = ctypes.c_void_p(256)
+    assert lib.bht_diag_stream(None, None, 1 << 20, sink, None) == bht.BHT_ERR_INVALID_ARG
+    assert lib.bht_diag_stream(ctypes.c_void_p(256), None, 8, sink, None) == bht.BHT_ERR_INVALID_ARG
+    assert lib.bht_diag_stream(ctypes.c_void_p(264), None, 1 << 20, sink, None) == bht.BHT_ERR_INVALID_ARG
+    assert lib.bht_diag_stream(ctypes.c_void_p(256), ctypes.c_void_p(260), 1 << 20, sink,
+                               None) == bht.BHT_ERR_INVALID_ARG
+    assert lib.bht_diag_stream(ctypes.c_void_p(256), None, 1 << 20, None, None) == bht.BHT_ERR_INVALID_ARG
+
+
 def test_library_hash64_equals_oracle():
     import paper_2108_07232_amd as bht
     Q = (1 << 61) - 1
