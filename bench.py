@@ -85,12 +85,15 @@ def algorithmic_bytes(probes, build=None):
     reads an 8-byte pair per key.
 
     build: statistics of a partitioned build (passes, slots per key,
-    evicted pairs per key, overflow bucket reads per key), whose bytes are
-    its streaming passes (each radix pass counts keys, 4 B, then reads and
-    writes pairs, 16 B), the placement (reads 8 B, writes every slot of the
-    table, 8 B per slot), the evicted pairs (written and read back, 16 B
-    each) and the overflow insertion (a probe plus a slot atomic per bucket
-    read)."""
+    evicted pairs per key, overflow bucket reads per key, padding pairs per
+    key of each radix pass), whose bytes are its streaming passes (each
+    radix pass counts keys, 4 B, then reads and writes pairs, 16 B), the
+    padding that completes 128-byte lines (a first-pass padding pair is
+    written, then counted and read by the second pass, 20 B; a second-pass
+    one written and read by the placement, 16 B), the placement (reads 8 B,
+    writes every slot of the table, 8 B per slot), the evicted pairs
+    (written and read back, 16 B each) and the overflow insertion (a probe
+    plus a slot atomic per bucket read)."""
     out = {
         "build": 8 + probes["insert"] * (128 + WRITE_GRANULE),
         "find_pos": 9 + 128 * probes["pos"],
@@ -99,6 +102,7 @@ def algorithmic_bytes(probes, build=None):
     }
     if build:
         out["build"] = (20 * build["passes"] + 8 + 8 * build["slots_per_key"]
+                        + 20 * build.get("pad1_per_key", 0) + 16 * build.get("pad2_per_key", 0)
                         + 16 * build["evicted_per_key"]
                         + build["overflow_probes_per_key"] * (128 + WRITE_GRANULE))
     return out
@@ -778,12 +782,14 @@ def run_lfsweep(args):
                 for k, v in find_ms.items():
                     ms[k].append(v)
         part, evicted, ovf_probes = bht.bht_build_stats(table.handle)
+        pads = bht.bht_build_padding(table.handle)
         m, b, _, table_bytes = table.info
         build_stats = None
         if part:
             build_stats = {"passes": partition_passes(m, b), "slots_per_key": m * b / n,
                            "evicted_per_key": evicted / n,
-                           "overflow_probes_per_key": ovf_probes / n}
+                           "overflow_probes_per_key": ovf_probes / n,
+                           "pad1_per_key": pads[0] / n, "pad2_per_key": pads[1] / n}
         total = torch.zeros(1, dtype=torch.int64, device=dev)
         st = bht.bht_build_counted(table.handle, d_keys, d_vals, total)
         probes = {"insert": int(total.item()) / n if st == bht.BHT_OK else None}
@@ -1336,6 +1342,7 @@ def run_headline(args):
     verified = {"queries_checked": 3 * n, "mismatches": mismatches,
                 "ok": all(v == 0 for v in mismatches.values())}
     part, evicted, ovf_probes = bht.bht_build_stats(table.handle)
+    pads = bht.bht_build_padding(table.handle)
 
     # probe counts of the timed layout: the instrumented find (untimed) on
     # each batch; the counts sum into the table's counter as well
@@ -1373,7 +1380,8 @@ def run_headline(args):
     build_stats = None
     if part:
         build_stats = {"passes": partition_passes(m, b), "slots_per_key": m * b / n,
-                       "evicted_per_key": evicted / n, "overflow_probes_per_key": ovf_probes / n}
+                       "evicted_per_key": evicted / n, "overflow_probes_per_key": ovf_probes / n,
+                       "pad1_per_key": pads[0] / n, "pad2_per_key": pads[1] / n}
     bytes_per = algorithmic_bytes(probes, build_stats)
 
     kernels = {}
@@ -1386,8 +1394,9 @@ def run_headline(args):
                          "bytes_per_key": round(bytes_per[name], 2),
                          "achieved_gbs": round(gbs, 1),
                          "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
-    kernels["build"]["bytes_basis"] = ("partitioned build's own traffic: radix passes, placement, "
-                                       "evicted pairs, overflow insertion" if build_stats else
+    kernels["build"]["bytes_basis"] = ("partitioned build's own traffic: radix passes, line "
+                                       "padding, placement, evicted pairs, overflow insertion"
+                                       if build_stats else
                                        "concurrent insertion: pair + probes x (bucket + write)")
     if probes.get("insert") and build_stats:
         # for comparison only: the same rate priced by the paper's cost model

@@ -178,6 +178,16 @@ bht_status bht_build_retry(bht_table* t, const void* d_keys, const void* d_value
 bht_status bht_build_stats(const bht_table* t, uint32_t* partitioned, uint64_t* evicted,
                            uint64_t* overflow_probes);
 
+/* Padding words of the last successful build's radix passes: a pass with
+ * at most 256 digits over 32-bit pairs rounds every (chunk, digit) range
+ * of its output up to whole 128-byte lines with the empty key (value 0),
+ * which the next step skips; *pass1_words and *pass2_words are the
+ * padding pairs the first and the second pass wrote (read back by the next
+ * step, so part of the build's traffic), 0 for a pass that did not pad or
+ * did not run, and both 0 for a concurrent build.  NOT_BUILT before a
+ * successful build. */
+bht_status bht_build_padding(const bht_table* t, uint64_t* pass1_words, uint64_t* pass2_words);
+
 /* Bytes of caller-owned workspace a partitioned build of n pairs into this
  * table needs (see bht_tuning's build_mode), or 0 when the table does not
  * take that path (schemes other than BCHT and CHT1, 64-bit keys, n = 0,

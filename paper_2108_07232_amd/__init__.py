@@ -95,6 +95,7 @@ _SIGS = {
     "bht_build_noalloc_max_bytes": (_u64, []),
     "bht_build_async_noalloc": (_st, [_p, _p, _p, _u64, _p]),
     "bht_build_stats": (_st, [_p, ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
+    "bht_build_padding": (_st, [_p, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "bht_params_from_seed": (_st, [_u64, ctypes.c_int, _u32, ctypes.POINTER(bht_params)]),
     "bht_build_retry": (_st, [_p, _p, _p, _u64, _u64, _u32, ctypes.POINTER(_u32), _p]),
     "bht_find_counted": (_st, [_p, _p, _u64, _p, _p, _p, _p]),
@@ -299,6 +300,13 @@ def bht_build_stats(table):
     _check(_lib.bht_build_stats(table, ctypes.byref(part), ctypes.byref(ev), ctypes.byref(pr)),
            "bht_build_stats")
     return bool(part.value), ev.value, pr.value
+
+
+def bht_build_padding(table):
+    """(first-pass, second-pass) padding pairs of the last build's radix passes."""
+    p1, p2 = _u64(0), _u64(0)
+    _check(_lib.bht_build_padding(table, ctypes.byref(p1), ctypes.byref(p2)), "bht_build_padding")
+    return p1.value, p2.value
 
 
 def bht_params_from_seed(seed: int, scheme, key_bits: int = 32) -> bht_params:

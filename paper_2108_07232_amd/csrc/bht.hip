@@ -36,7 +36,7 @@ struct bht_table {
   uint64_t words;       // uint64 words in the slot array
   uint64_t slots;       // pair capacity (both levels)
   uint32_t* d_status;   // [0] flags; lives after the slot array
-  uint32_t h_status[4]; // host copy
+  uint32_t h_status[8]; // host copy
   bool owns_memory;     // slot array allocated by the library
   uint64_t n_stored;
   uint64_t pending_n;
@@ -55,6 +55,8 @@ struct bht_table {
   bool last_partitioned;   // the last successful build took the partitioned path
   uint64_t last_evicted;   // ... and evicted this many pairs on chip
   uint64_t last_probes;    // ... and read this many buckets inserting them
+  uint64_t last_pad1;      // ... and its radix passes wrote this much padding
+  uint64_t last_pad2;
   uint64_t counted_build_probes;  // bucket reads of the last build, if it was counted
   uint64_t find_probe_base;       // find-probe counter value at the last stats read
 };
@@ -445,6 +447,14 @@ bool part_kernels(const bht_table* t, uint32_t w, PartKernels* k) {
   return false;
 }
 
+// Padding words a line-writing pass over `chunks` chunks of `fan` digits
+// adds to n pairs, at most: under a line per non-empty (chunk, digit) range.
+uint64_t line_pad_bound(uint64_t chunks, uint64_t fan, uint64_t n) {
+  return std::min<uint64_t>(chunks * fan, n) * (kLineWords - 1);
+}
+
+uint64_t round_to_line(uint64_t words) { return (words + kLineWords - 1) / kLineWords * kLineWords; }
+
 uint32_t log2_exact(uint64_t x) {
   uint32_t r = 0;
   while ((1ull << r) < x) ++r;
@@ -477,14 +487,32 @@ bool part_plan(const bht_table* t, uint64_t n, PartPlan* P) {
     if (fan1 > kMaxFan) return false;
     P->fan1 = (uint32_t)fan1;
   }
+  // Passes of at most 256 digits over 32-bit pairs write whole lines, while
+  // positions, padding included, stay below 2^32 and (two passes) the
+  // padded first-pass output still fits the slot array it is written to.
+  if (kScatterLines && t->key_bits == 32) {
+    const uint64_t chunks1 = (n + P->chunk - 1) / P->chunk;
+    const uint64_t in2 = n + line_pad_bound(chunks1, P->fan1, n);
+    if (P->levels == 1) {
+      P->lines1 = P->fan1 <= kLineMaxFan && in2 < (1ull << 32);
+    } else {
+      const uint64_t mid = round_to_line(in2);
+      P->lines1 = P->fan1 <= kLineMaxFan && mid <= t->slots && mid < (1ull << 32);
+      const uint64_t in = P->lines1 ? in2 : n;
+      const uint64_t chunks2 = in / P->chunk + P->fan1;
+      P->lines2 = in + chunks2 * kLinePadPerChunk2 < (1ull << 32);
+    }
+  }
   return true;
 }
 
 // Workspace carve-up (256-byte aligned pieces) for n pairs under plan P.
+// mid_words: words of each first-pass output array (of two passes; keys,
+// then values, in the slot array); keys/vals hold out_words words each.
 struct PartLayout {
   uint64_t hist1, hist2, total1, cursor1, seg_start, seg_len, chunk_first, total2, cursor2,
       bin_start, bin_len, ovf_len, head, keys, vals, bytes;
-  uint64_t chunks1, chunks2;
+  uint64_t chunks1, chunks2, mid_words, out_words;
 };
 
 PartLayout part_layout(const PartPlan& P, uint64_t n, uint32_t word_bytes = 4) {
@@ -496,7 +524,11 @@ PartLayout part_layout(const PartPlan& P, uint64_t n, uint32_t word_bytes = 4) {
     return at;
   };
   L.chunks1 = (n + P.chunk - 1) / P.chunk;
-  L.chunks2 = P.levels == 2 ? n / P.chunk + P.fan1 : 0;
+  // first-pass output words, padding included
+  const uint64_t in2 = n + (P.lines1 ? line_pad_bound(L.chunks1, P.fan1, n) : 0);
+  L.chunks2 = P.levels == 2 ? in2 / P.chunk + P.fan1 : 0;
+  L.mid_words = P.levels == 2 ? (P.lines1 ? round_to_line(in2) : n) : 0;
+  L.out_words = in2 + (P.lines2 ? L.chunks2 * kLinePadPerChunk2 : 0);
   L.hist1 = take(L.chunks1 * P.fan1 * 4);
   L.hist2 = take(L.chunks2 * kFan2 * 4);
   L.total1 = take(P.fan1 * 8ull);
@@ -510,8 +542,8 @@ PartLayout part_layout(const PartPlan& P, uint64_t n, uint32_t word_bytes = 4) {
   L.bin_len = take(P.nbins * 8ull);
   L.ovf_len = take(P.nbins * 4ull);
   L.head = take(4);
-  L.keys = take(n * word_bytes);
-  L.vals = take(n * word_bytes);
+  L.keys = take(L.out_words * word_bytes);
+  L.vals = take(L.out_words * word_bytes);
   L.bytes = off;
   return L;
 }
@@ -589,9 +621,11 @@ void launch_radix(const PartPlan& P, const PartMeta& M, const PartLayout& L, con
                   uint32_t* status, hipStream_t st) {
   void (*hist)(PartPassT<T>);
   void (*scatter)(PartPassT<T>);
+  void (*scatter_lines)(PartPassT<T>) = nullptr;
   if constexpr (sizeof(T) == 4) {
     hist = part_hist_kernel<uint32_t>;
     scatter = part_scatter_kernel<uint32_t>;
+    scatter_lines = part_scatter_lines_kernel;
   } else {
     hist = part_hist64_kernel;
     scatter = part_scatter64_kernel;
@@ -605,12 +639,14 @@ void launch_radix(const PartPlan& P, const PartMeta& M, const PartLayout& L, con
   p1.n = n;
   p1.level = 1;
   p1.fan = P.fan1;
+  p1.lines = P.lines1;
+  p1.padded = 0;
   p1.status = status;
   p1.P = P;
   p1.M = M;
   hist<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
-  part_scan1_kernel<<<1, kPartBlock, 0, st>>>(P, M);
-  scatter<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
+  part_scan1_kernel<<<1, kPartBlock, 0, st>>>(P, M, status);
+  (P.lines1 ? scatter_lines : scatter)<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
   if (P.levels == 2) {
     PartPassT<T> p2 = p1;
     p2.in_k = mid_k;
@@ -619,9 +655,11 @@ void launch_radix(const PartPlan& P, const PartMeta& M, const PartLayout& L, con
     p2.out_v = vals2;
     p2.level = 2;
     p2.fan = kFan2;
+    p2.lines = P.lines2;
+    p2.padded = P.lines1;
     hist<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
-    part_scan2_kernel<<<P.fan1, kPartBlock, 0, st>>>(P, M);
-    scatter<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
+    part_scan2_kernel<<<P.fan1, kPartBlock, 0, st>>>(P, M, status);
+    (P.lines2 ? scatter_lines : scatter)<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
   }
 }
 
@@ -694,10 +732,11 @@ bht_status build32_partitioned(bht_table* t, const uint32_t* keys, const uint32_
   uint32_t* keys2 = reinterpret_cast<uint32_t*>(w + L.keys);
   uint32_t* vals2 = reinterpret_cast<uint32_t*>(w + L.vals);
   // With two passes the first pass writes into the table's slot array,
-  // which holds at least n pairs and is rewritten whole by the placement
-  // (and a two-level iceberg table's secondary array by the reset below).
+  // which holds at least mid_words pairs (the plan checks it when the pass
+  // pads) and is rewritten whole by the placement (and a two-level iceberg
+  // table's secondary array by the reset below).
   uint32_t* mid_k = reinterpret_cast<uint32_t*>(t->d_slots);
-  uint32_t* mid_v = mid_k + n;
+  uint32_t* mid_v = mid_k + L.mid_words;
 
   if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
   launch_radix<uint32_t>(P, M, L, keys, vals, n, mid_k, mid_v, keys2, vals2, t->d_status, st);
@@ -1128,7 +1167,8 @@ bht_status bht_build_wait(bht_table* t, void* stream) {
   if (!t) return fail(BHT_ERR_INVALID_ARG, "null table");
   if (!t->pending) return t->built ? BHT_OK : fail(BHT_ERR_NOT_BUILT, "no build pending");
   hipStream_t st = as_stream(stream);
-  HIP_TRY(hipMemcpyAsync(t->h_status, t->d_status, 16, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(t->h_status, t->d_status, sizeof(t->h_status), hipMemcpyDeviceToHost,
+                         st));
   HIP_TRY(hipStreamSynchronize(st));
   t->pending = false;
   const uint32_t flags = t->h_status[0];
@@ -1143,6 +1183,21 @@ bht_status bht_build_wait(bht_table* t, void* stream) {
   t->last_probes = t->pending_partitioned
                        ? ((uint64_t)t->h_status[3] << 32 | t->h_status[2])
                        : 0;
+  // words each radix pass wrote (0 when it did not run), less the pairs
+  auto pad = [t](int w) {
+    const uint64_t words = (uint64_t)t->h_status[w + 1] << 32 | t->h_status[w];
+    return t->pending_partitioned && words > t->n_stored ? words - t->n_stored : 0;
+  };
+  t->last_pad1 = pad(kStatusPass1Words);
+  t->last_pad2 = pad(kStatusPass2Words);
+  return BHT_OK;
+}
+
+bht_status bht_build_padding(const bht_table* t, uint64_t* pass1_words, uint64_t* pass2_words) {
+  if (!t || !pass1_words || !pass2_words) return fail(BHT_ERR_INVALID_ARG, "null argument");
+  if (!t->built) return fail(BHT_ERR_NOT_BUILT, "no successful build");
+  *pass1_words = t->last_pad1;
+  *pass2_words = t->last_pad2;
   return BHT_OK;
 }
 

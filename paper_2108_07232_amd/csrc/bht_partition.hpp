@@ -15,6 +15,10 @@
 //      most 1024, then 256); each pass counts digits per chunk of pairs,
 //      reserves output ranges per (chunk, digit), and writes each sub-tile
 //      in digit order staged through LDS, so stores are contiguous runs;
+//      with at most 256 digits a pass writes whole 128-byte lines only: a
+//      digit's elements that do not fill a line wait in LDS for the next
+//      sub-tile, and each (chunk, digit) range is padded to whole lines with
+//      the empty key, which later steps skip;
 //   2. bin placement: one workgroup per bin builds its buckets in LDS,
 //      placing each pair in its first bucket at the next free slot
 //      (a local atomic on the bucket's load); a pair that finds its first
@@ -55,6 +59,10 @@ namespace bht {
 #ifndef BHT_SCATTER_STAGE_DIGITS
 #define BHT_SCATTER_STAGE_DIGITS 1
 #endif
+#ifndef BHT_SCATTER_LINES
+#define BHT_SCATTER_LINES 1
+#endif
+constexpr bool kScatterLines = BHT_SCATTER_LINES != 0;         // line-writing scatter where it applies
 constexpr int kScatterBlocksPerCU = BHT_SCATTER_BLOCKS_PER_CU;   // occupancy the scatter is compiled for
 constexpr bool kScatterStageDigits = BHT_SCATTER_STAGE_DIGITS != 0; // digits staged beside the pairs
 constexpr int kPartBlock = 256;                        // threads per scan block
@@ -63,6 +71,9 @@ constexpr int kPartSub = BHT_PASS_PER * kPassBlock;   // pairs per sub-tile (4-b
 constexpr uint32_t kPartChunkMax = 4 * kPartSub;       // pairs per partition block, at most
 constexpr uint32_t kMaxFan = 1024;                     // digits of the first pass, at most
 constexpr uint32_t kFan2 = 256;                        // digits of the second pass
+constexpr int kLineSub = 8 * kPassBlock;               // pairs per sub-tile of the line-writing scatter
+constexpr uint32_t kLineMaxFan = 256;                  // its digits, at most (carried lines fill 64 KB)
+constexpr uint32_t kLineWords = 32;                    // 4-byte words per 128-byte line
 constexpr int kBinBlock = 512;                         // threads per bin placement block
 constexpr int kBinPer = 16;                            // pairs per thread per round
 
@@ -79,7 +90,14 @@ struct PartPlan {
   uint32_t fan1;        // digits of the first pass
   uint32_t nbins;
   uint32_t chunk;       // pairs per partition block (a multiple of the sub-tile)
+  uint32_t lines1;      // the first pass writes whole lines (ranges padded with the empty key)
+  uint32_t lines2;      // the same for the second pass
 };
+
+// Words of a (chunk, digit) range of c pairs when a pass writes whole lines.
+__host__ __device__ __forceinline__ uint32_t line_pad(uint32_t c) {
+  return (c + kLineWords - 1) & ~(kLineWords - 1);
+}
 
 // Device metadata of one partitioned build (one allocation, see the host).
 struct PartMeta {
@@ -110,6 +128,8 @@ struct PartPassT {
   uint64_t n;
   uint32_t level;
   uint32_t fan;
+  uint32_t lines;      // this pass writes whole lines (line-writing scatter)
+  uint32_t padded;     // its input may hold padding (the empty key), skipped
   uint32_t* status;
   PartPlan P;
   PartMeta M;
@@ -208,7 +228,7 @@ __global__ void part_clear_kernel(PartMeta M, uint32_t fan1, uint32_t levels,
   if (levels == 2)
     for (uint32_t j = i; j < fan1 * kFan2; j += stride) M.total2[j] = 0;
   if (i == 0) *M.head = 0;
-  if (i < 4) status[i] = 0;
+  if (i < 8) status[i] = 0;
 }
 
 // Keys reserved by the tables (the empty marker; for 64-bit keys also the
@@ -222,13 +242,16 @@ template <typename T>
 constexpr int sub_tile() { return sizeof(T) == 4 ? kPartSub : kPartSub / 2; }
 
 // Digit counts of the pairs [begin, end) of in_k: stored in hrow (for the
-// scatter's reservations) and added to tot; returns whether the range held
-// a reserved key.  Every thread of the block calls it.
+// scatter's reservations) and added to tot, rounded up to whole lines when
+// the scatter writes lines (pad_totals); returns whether the range held a
+// reserved key.  With skip_pads, empty keys are padding and not counted.
+// Every thread of the block calls it.
 template <typename T, typename DigitFn>
 __device__ __forceinline__ bool hist_range(const T* __restrict__ in_k, uint64_t begin,
                                            uint64_t end, uint32_t fan, DigitFn digit,
                                            uint32_t* __restrict__ hrow,
-                                           unsigned long long* __restrict__ tot) {
+                                           unsigned long long* __restrict__ tot,
+                                           bool skip_pads = false, bool pad_totals = false) {
   __shared__ uint32_t cnt[kMaxFan];
   for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) cnt[d] = 0;
   __syncthreads();
@@ -253,7 +276,7 @@ __device__ __forceinline__ bool hist_range(const T* __restrict__ in_k, uint64_t 
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         const uint32_t o = base + j * kPassBlock + threadIdx.x;
-        if (FULL || o < len) {
+        if ((FULL || o < len) && !(skip_pads && reserved_key(k[j]))) {
           sentinel |= reserved_key(k[j]);
           atomicAdd(&cnt[digit(k[j])], 1u);
         }
@@ -266,7 +289,7 @@ __device__ __forceinline__ bool hist_range(const T* __restrict__ in_k, uint64_t 
   for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) {
     const uint32_t c = cnt[d];
     hrow[d] = c;
-    if (c) atomicAdd(&tot[d], (unsigned long long)c);
+    if (c) atomicAdd(&tot[d], (unsigned long long)(pad_totals ? line_pad(c) : c));
   }
   return sentinel;
 }
@@ -283,17 +306,27 @@ __global__ __launch_bounds__(kPassBlock) void part_hist_kernel(PartPassT<T> p) {
   const PartPlan& P = p.P;
   const uint32_t level = p.level;
   const bool sentinel = hist_range(p.in_k, begin, end, p.fan,
-                                   [&](T k) { return part_digit(P, level, k); }, h, tot);
+                                   [&](T k) { return part_digit(P, level, k); }, h, tot,
+                                   p.padded != 0, p.lines != 0);
   if (level == 1 && sentinel) atomicOr(p.status, kFlagSentinel);
 }
 
+// Status words 4-5 and 6-7 (64-bit): words the first and the second pass
+// write, padding included.
+constexpr int kStatusPass1Words = 4;
+constexpr int kStatusPass2Words = 6;
+
 // First-pass totals -> output ranges.  One block.  With one pass the digits
 // are the bins; with two, the ranges of the second pass and its chunk counts.
-__global__ __launch_bounds__(kPartBlock) void part_scan1_kernel(PartPlan P, PartMeta M) {
+__global__ __launch_bounds__(kPartBlock) void part_scan1_kernel(PartPlan P, PartMeta M,
+                                                                uint32_t* __restrict__ status) {
   __shared__ unsigned long long wt[kPartBlock / 64];
   __shared__ unsigned long long base[kMaxFan];
   __shared__ unsigned long long chunks[kMaxFan];
-  block_exclusive_scan<kPartBlock, unsigned long long>(M.total1, base, P.fan1, wt);
+  const unsigned long long words =
+      block_exclusive_scan<kPartBlock, unsigned long long>(M.total1, base, P.fan1, wt);
+  if (threadIdx.x == 0)
+    *reinterpret_cast<unsigned long long*>(status + kStatusPass1Words) = words;
   for (uint32_t d = threadIdx.x; d < P.fan1; d += kPartBlock) {
     const unsigned long long c = M.total1[d];
     M.cursor1[d] = base[d];
@@ -314,15 +347,25 @@ __global__ __launch_bounds__(kPartBlock) void part_scan1_kernel(PartPlan P, Part
   if (threadIdx.x == 0) M.chunk_first[P.fan1] = (uint32_t)total;
 }
 
-// Second-pass totals -> bin ranges.  One block per first-pass range.
-__global__ __launch_bounds__(kPartBlock) void part_scan2_kernel(PartPlan P, PartMeta M) {
+// Words of padding a line-writing second pass adds to one chunk, at most.
+constexpr uint64_t kLinePadPerChunk2 = (uint64_t)kFan2 * (kLineWords - 1);
+
+// Second-pass totals -> bin ranges.  One block per first-pass range.  The
+// range's output starts where its input does, shifted, when the pass
+// writes lines, by the most padding the earlier ranges' chunks can add.
+__global__ __launch_bounds__(kPartBlock) void part_scan2_kernel(PartPlan P, PartMeta M,
+                                                                uint32_t* __restrict__ status) {
   __shared__ unsigned long long wt[kPartBlock / 64];
   __shared__ unsigned long long base[kFan2];
   const uint32_t s = blockIdx.x;
   const unsigned long long* tot = M.total2 + (uint64_t)s * kFan2;
-  block_exclusive_scan<kPartBlock, unsigned long long>(tot, base, kFan2, wt);
+  const unsigned long long words =
+      block_exclusive_scan<kPartBlock, unsigned long long>(tot, base, kFan2, wt);
+  if (threadIdx.x == 0 && words)
+    atomicAdd(reinterpret_cast<unsigned long long*>(status + kStatusPass2Words), words);
   const uint32_t d = threadIdx.x;          // kPartBlock == kFan2
-  const unsigned long long pos = M.seg_start[s] + base[d];
+  const unsigned long long shift = P.lines2 ? kLinePadPerChunk2 * M.chunk_first[s] : 0ull;
+  const unsigned long long pos = M.seg_start[s] + shift + base[d];
   M.cursor2[(uint64_t)s * kFan2 + d] = pos;
   const uint64_t bin = (uint64_t)s * kFan2 + d;
   if (bin < P.nbins) {
@@ -478,6 +521,175 @@ __global__ __launch_bounds__(kPassBlock, kScatterBlocksPerCU) void part_scatter_
                 [&](T k) { return part_digit(P, level, k); }, h, cur, p.out_k, p.out_v);
 }
 
+// Per-digit line counts packed beside the digit counts, for one scan: the
+// digit's new pairs (< 2^16) in the low half, the whole lines it writes in
+// this sub-tile in the high half (all pairs and pending words when the
+// sub-tile ends the range, else only the full lines).
+struct LinePack {
+  const uint32_t* cnt;
+  const uint32_t* carry;
+  bool last;
+  __device__ __forceinline__ uint32_t operator[](uint32_t d) const {
+    const uint32_t tot = carry[d] + cnt[d];
+    const uint32_t lines = last ? (tot + kLineWords - 1) / kLineWords : tot / kLineWords;
+    return (lines << 16) | cnt[d];
+  }
+};
+
+// scatter_range for at most kLineMaxFan digits that stores whole 128-byte
+// lines only.  Each digit's range of this chunk (hrow[d] pairs) is reserved
+// rounded up to whole lines at a line-aligned cursor.  Per sub-tile the
+// pairs are ranked and staged by digit as in scatter_range; a digit's
+// output then continues with the words carried from the previous sub-tile
+// followed by its staged pairs, and only the lines that are full are
+// written (half a wave per line, from a descriptor built per line); the
+// remainder (< 32 words) is carried in LDS.  The range's last sub-tile
+// writes the remainder too, padded with the empty key and value 0.  With
+// padded input, empty keys are padding and skipped.  Partial lines, each
+// written twice from different times or different workgroups, are what
+// slows the plain scatter.  Every thread of the block calls it.
+template <typename DigitFn>
+__device__ __forceinline__ void scatter_lines_range(const uint32_t* __restrict__ in_k,
+                                                    const uint32_t* __restrict__ in_v,
+                                                    uint64_t begin, uint64_t end, uint32_t fan,
+                                                    bool padded, DigitFn digit,
+                                                    const uint32_t* __restrict__ hrow,
+                                                    unsigned long long* __restrict__ cur,
+                                                    uint32_t* __restrict__ out_k,
+                                                    uint32_t* __restrict__ out_v) {
+  constexpr int SUB = kLineSub;
+  constexpr int PER = SUB / kPassBlock;
+  constexpr uint32_t LW = kLineWords;
+  constexpr uint32_t FMAX = kLineMaxFan;
+  // lines of one sub-tile, at most: every word once, plus a partial line per digit
+  constexpr int MAXLINES = (SUB + FMAX * (LW - 1)) / LW + FMAX;
+  static_assert(SUB < (1 << 16) && MAXLINES < (1 << 16), "packed scan fields");
+  static_assert(kPassBlock % LW == 0, "half waves per block");
+  // staged pairs [0, SUB), then LW carried pairs per digit, key and value
+  // side by side (one 8-byte LDS access per pair)
+  __shared__ uint2 skv[SUB + FMAX * LW];
+  __shared__ uint32_t cnt[FMAX];          // new pairs per digit in this sub-tile
+  __shared__ uint32_t pre[FMAX];          // packed exclusive prefix (first line, first staged pair)
+  __shared__ uint32_t carry[FMAX];        // carried words per digit
+  __shared__ uint32_t run[FMAX];          // next output position per digit (line-aligned)
+  // per line: output position; index (into skv) of the staged pair for
+  // lane 0; index of the carried word for lane 0; lanes below .w & 63 take
+  // carried words, lanes from .w >> 8 on write padding
+  __shared__ uint4 line_desc[MAXLINES];
+  __shared__ uint32_t wt[kPassBlock / 64];
+  const uint32_t tid = threadIdx.x, hl = tid / LW, l = tid % LW;
+  for (uint32_t d = tid; d < fan; d += kPassBlock) {
+    const uint32_t c = hrow[d];
+    run[d] = c ? (uint32_t)atomicAdd(&cur[d], (unsigned long long)line_pad(c)) : 0u;
+    cnt[d] = 0;
+    carry[d] = 0;
+  }
+  const uint32_t* __restrict__ kb = in_k + begin;
+  const uint32_t* __restrict__ vb = in_v + begin;
+  const uint32_t len = (uint32_t)(end - begin);
+  const uint32_t last_i = len - 1;
+  uint32_t k[PER], v[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const uint32_t o = j * kPassBlock + tid;
+    k[j] = kb[o < len ? o : last_i];
+    v[j] = vb[o < len ? o : last_i];
+  }
+  for (uint32_t sub = 0; sub < len; sub += SUB) {
+    uint32_t nk[PER], nv[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const uint32_t o = sub + SUB + j * kPassBlock + tid;
+      nk[j] = kb[o < len ? o : last_i];
+      nv[j] = vb[o < len ? o : last_i];
+    }
+    // the previous sub-tile's carries and cleared counts are in place
+    __syncthreads();
+    const uint32_t count = len - sub < (uint32_t)SUB ? len - sub : (uint32_t)SUB;
+    const bool last = len - sub <= (uint32_t)SUB;
+    // rank within the digit (< 2^13) above the digit (< 2^8); ~0 = no pair
+    uint32_t rd[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const uint32_t i = j * kPassBlock + tid;
+      rd[j] = ~0u;
+      if (i < count && !(padded && k[j] == kEmptyKey)) {
+        const uint32_t d = digit(k[j]);
+        rd[j] = (atomicAdd(&cnt[d], 1u) << 8) | d;
+      }
+    }
+    __syncthreads();
+    const uint32_t total =
+        block_exclusive_scan<kPassBlock, uint32_t>(LinePack{cnt, carry, last}, pre, fan, wt);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (rd[j] != ~0u) {
+        const uint32_t d = rd[j] & 255u;
+        const uint32_t pos = (pre[d] & 0xFFFFu) + (rd[j] >> 8);
+        skv[pos] = make_uint2(k[j], v[j]);
+      }
+    }
+    for (uint32_t d = tid; d < fan; d += kPassBlock) {
+      const uint32_t p = pre[d], cf = carry[d], c = cnt[d];
+      const uint32_t first = p >> 16;
+      const uint32_t lines = (LinePack{cnt, carry, last}[d]) >> 16;
+      for (uint32_t q = 0; q < lines; ++q) {
+        // words of this line: e = q * LW + lane over [carried, staged, padding)
+        const uint32_t e0 = q * LW;
+        const uint32_t nc = cf > e0 ? cf - e0 : 0u;                 // carried lanes
+        const uint32_t nw = cf + c > e0 ? min(cf + c - e0, LW) : 0u; // carried + staged lanes
+        line_desc[first + q] = make_uint4(run[d] + e0, (p & 0xFFFFu) + e0 - cf,
+                                          SUB + d * LW + e0, nc | (nw << 8));
+      }
+    }
+    __syncthreads();
+    // whole lines: carried words first, then the staged pairs, then padding
+    const uint32_t nlines = total >> 16;
+    for (uint32_t it = hl; it < nlines; it += kPassBlock / LW) {
+      const uint4 ld = line_desc[it];
+      uint2 kv = make_uint2(kEmptyKey, 0u);
+      if (l < (ld.w >> 8)) kv = skv[l < (ld.w & 63u) ? ld.z + l : ld.y + l];
+      out_k[ld.x + l] = kv.x;
+      out_v[ld.x + l] = kv.y;
+    }
+    __syncthreads();
+    // carry what does not fill a line (half a wave per digit); the digit's
+    // output advances by the lines written and its count clears
+    for (uint32_t d = hl; d < fan; d += kPassBlock / LW) {
+      const uint32_t cf = carry[d], c = cnt[d], tot = cf + c;
+      const uint32_t lines = last ? (tot + LW - 1) / LW : tot / LW;
+      const uint32_t nc = last ? 0u : tot - lines * LW;
+      const uint32_t e = lines * LW + l;
+      if (l < nc && e >= cf) {
+        skv[SUB + d * LW + l] = skv[(pre[d] & 0xFFFFu) + e - cf];
+      }
+      if (l == 0) {
+        run[d] += lines * LW;
+        carry[d] = nc;
+        cnt[d] = 0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      k[j] = nk[j];
+      v[j] = nv[j];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kPassBlock, 1) void part_scatter_lines_kernel(PartPassT<uint32_t> p) {
+  uint32_t seg;
+  uint64_t begin, end;
+  if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
+  const uint32_t* h = (p.level == 1 ? p.M.hist1 : p.M.hist2) + (uint64_t)blockIdx.x * p.fan;
+  unsigned long long* cur = p.level == 1 ? p.M.cursor1 : p.M.cursor2 + (uint64_t)seg * kFan2;
+  const PartPlan& P = p.P;
+  const uint32_t level = p.level;
+  scatter_lines_range(p.in_k, p.in_v, begin, end, p.fan, p.padded != 0,
+                      [&](uint32_t k) { return part_digit(P, level, k); }, h, cur, p.out_k,
+                      p.out_v);
+}
+
 struct BinArgs {
   uint64_t* slots;               // the table
   uint32_t* keys;                // partitioned pairs; evicted pairs are written back in place
@@ -549,7 +761,9 @@ __device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
       // claims of a thread's pairs issue back to back.  lb < nb by
       // construction of the partition; otherwise the build fails.
       const uint32_t lb = hash32(H, 0, k[j]) - (uint32_t)first;
-      const bool valid = i < n_bin;
+      // the empty key marks padding of a line-writing pass (a caller's
+      // empty key has already failed the build)
+      const bool valid = i < n_bin && k[j] != kEmptyKey;
       const bool inside = lb < nb;
       if (valid && !inside) flags |= kFlagFailed;
       const bool claim = valid && inside;

@@ -31,6 +31,11 @@ def test_partitioned_build_bytes_at_the_headline_size():
     expect = 2 * (4 + 8 + 8) + 8 + 8 * m * 16 / n + 16 * 0.0568 + 0.1025 * (128 + 64)
     assert b["build"] == pytest.approx(expect)
     assert b["build"] == pytest.approx(77.5, abs=0.05)
+    # padding that completes lines: a first-pass pair moves 20 B (written,
+    # counted, read), a second-pass pair 16 B (written, read by the placement)
+    padded = dict(stats, pad1_per_key=0.034, pad2_per_key=0.067)
+    b2 = bench.algorithmic_bytes({"insert": 1.1, "pos": 1, "neg": 2, "mix": 1.5}, padded)
+    assert b2["build"] == pytest.approx(expect + 20 * 0.034 + 16 * 0.067)
 
 
 @pytest.mark.parametrize("n,lf,b,passes", [

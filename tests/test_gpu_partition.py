@@ -1,8 +1,9 @@
 """GPU parity of the partitioned build (radix passes by first-bucket region,
 first-bucket placement in on-chip memory, cuckoo insertion of the rest).
 
-The layout it produces is the serial cuckoo algorithm's for one insertion
-order, so it is judged like every GPU layout: the oracle's invariant checker
+The insertion runs under a deferred-victim schedule (first-bucket claims
+and on-chip exchanges, then the evicted pairs' chains concurrently), and
+its layout is judged like every GPU layout: the oracle's invariant checker
 (each pair stored once, in a candidate bucket, occupied slots a prefix,
 early-exit property) and lookups equal to brute force, bit for bit."""
 import numpy as np
@@ -90,6 +91,35 @@ def test_partitioned_build_two_passes(scheme, b, n, lf):
     assert plan_levels(params.m, b) == 2
     t, st = build_partitioned(params, keys, vals)
     assert st == bht().BHT_OK, bht().bht_status_string(st)
+    check_table(t, params, keys, vals, n_queries=1 << 21)
+    # both passes (at most 256 digits each) pad their ranges to whole
+    # 128-byte lines: each pass writes a multiple of 32 words, less than a
+    # line more per (chunk, digit) range
+    pad1, pad2 = bht().bht_build_padding(t.handle)
+    ranges = -(-n // 16384) * 256
+    for pad in (pad1, pad2):
+        assert 0 < pad <= 31 * ranges and (n + pad) % 32 == 0
+    t.close()
+
+
+def test_partitioned_first_pass_unpadded_when_slots_are_short():
+    """At 2^26 pairs and LF 0.985 the padded first-pass output could exceed
+    the slot array it is written to, so only the second pass pads; the
+    layout is valid and lookups equal brute force."""
+    B = bht()
+    n = 1 << 26
+    keys, vals = workload(n, 13)
+    for s in range(4):
+        params = oracle.params_for("bcht", n, 0.985, 620 + s)
+        t, st = build_partitioned(params, keys, vals)
+        if st == B.BHT_OK:
+            break
+        assert st == B.BHT_ERR_BUILD_FAILED
+        t.close()
+    else:
+        pytest.fail("no partitioned build succeeded")
+    pad1, pad2 = B.bht_build_padding(t.handle)
+    assert pad1 == 0 and pad2 > 0 and (n + pad2) % 32 == 0
     check_table(t, params, keys, vals, n_queries=1 << 21)
     t.close()
 
@@ -200,6 +230,7 @@ def test_eviction_count_equals_first_bucket_overflow(b, n, lf):
     t, st = build_partitioned(params, keys, vals, mode="concurrent")
     assert st == B.BHT_OK
     assert B.bht_build_stats(t.handle) == (False, 0, 0)
+    assert B.bht_build_padding(t.handle) == (0, 0)
     t.close()
 
 
