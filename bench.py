@@ -47,6 +47,8 @@ def parse():
                          "BCHT, BP2HT, two-level iceberg, 1CHT and 64-bit BCHT")
     ap.add_argument("--only", default=None,
                     help="schemes workload: comma-separated scheme names to run (default all)")
+    ap.add_argument("--lfs", default=None,
+                    help="lfsweep workload: comma-separated load factors (default the sweep)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--log2n", type=int, default=28)
@@ -740,7 +742,7 @@ def run_lfsweep(args):
     out_f = torch.empty(n, dtype=torch.uint8, device=dev)
     results = []
     seed = args.seed
-    for lf in LF_SWEEP:
+    for lf in ([float(x) for x in args.lfs.split(",")] if args.lfs else LF_SWEEP):
         cap = datagen.capacity_for(n, lf)
         table, failures, max_chain = None, 0, 128
         while table is None and max_chain <= 4096:

@@ -488,19 +488,28 @@ bool part_plan(const bht_table* t, uint64_t n, PartPlan* P) {
     P->fan1 = (uint32_t)fan1;
   }
   // Passes of at most 256 digits over 32-bit pairs write whole lines, while
-  // positions, padding included, stay below 2^32 and (two passes) the
+  // the padding they add is expected to stay under 8% of the pairs (half a
+  // line per (chunk, digit) range; small tables have small chunks), the
+  // positions, padding included, stay below 2^32, and (two passes) the
   // padded first-pass output still fits the slot array it is written to.
+  // At 2^24 pairs a padded second pass (12% padding) is no faster than the
+  // plain scatter; at 2^25 (6%) it is 8% faster.
   if (kScatterLines && t->key_bits == 32) {
+    auto light = [n](uint64_t chunks, uint64_t fan) {
+      return line_pad_bound(chunks, fan, n) <= n * 16 / 100;
+    };
     const uint64_t chunks1 = (n + P->chunk - 1) / P->chunk;
     const uint64_t in2 = n + line_pad_bound(chunks1, P->fan1, n);
     if (P->levels == 1) {
-      P->lines1 = P->fan1 <= kLineMaxFan && in2 < (1ull << 32);
+      P->lines1 = P->fan1 <= kLineMaxFan && light(chunks1, P->fan1) && in2 < (1ull << 32);
     } else {
       const uint64_t mid = round_to_line(in2);
-      P->lines1 = P->fan1 <= kLineMaxFan && mid <= t->slots && mid < (1ull << 32);
+      P->lines1 = P->fan1 <= kLineMaxFan && light(chunks1, P->fan1) && mid <= t->slots &&
+                  mid < (1ull << 32);
       const uint64_t in = P->lines1 ? in2 : n;
       const uint64_t chunks2 = in / P->chunk + P->fan1;
-      P->lines2 = in + chunks2 * kLinePadPerChunk2 < (1ull << 32);
+      P->lines2 = light(chunks2, kFan2) &&
+                  in + chunks2 * kLinePadPerChunk2 + kLineWords * (P->fan1 + 1) < (1ull << 32);
     }
   }
   return true;
@@ -528,7 +537,7 @@ PartLayout part_layout(const PartPlan& P, uint64_t n, uint32_t word_bytes = 4) {
   const uint64_t in2 = n + (P.lines1 ? line_pad_bound(L.chunks1, P.fan1, n) : 0);
   L.chunks2 = P.levels == 2 ? in2 / P.chunk + P.fan1 : 0;
   L.mid_words = P.levels == 2 ? (P.lines1 ? round_to_line(in2) : n) : 0;
-  L.out_words = in2 + (P.lines2 ? L.chunks2 * kLinePadPerChunk2 : 0);
+  L.out_words = in2 + (P.lines2 ? L.chunks2 * kLinePadPerChunk2 + kLineWords * (P.fan1 + 1) : 0);
   L.hist1 = take(L.chunks1 * P.fan1 * 4);
   L.hist2 = take(L.chunks2 * kFan2 * 4);
   L.total1 = take(P.fan1 * 8ull);
@@ -1666,7 +1675,7 @@ bht_status bht_batch_create(const bht_batch_entry* entries, uint32_t count, uint
       if (nb > kMaxFan || t->build_mode == BHT_BUILD_CONCURRENT) part = false;
       n_all += entries[i].n_keys;
       bins += nb;
-      counters += ((entries[i].n_keys + kPartChunkMax - 1) / kPartChunkMax) * nb;
+      counters += ((entries[i].n_keys + kBatchChunk - 1) / kBatchChunk) * nb;
     }
     if (n_all >= (1ull << 32) || bins >= (1ull << 32)) part = false;
     if (part) {
@@ -1681,8 +1690,8 @@ bht_status bht_batch_create(const bht_batch_entry* entries, uint32_t count, uint
         const uint32_t nb = (uint32_t)((t->m + R - 1) / R);
         parts[i] = {key_off, hist_off, (uint32_t)bin_table.size(), nb};
         uint32_t local = 0;
-        for (uint64_t s0 = 0; s0 < n; s0 += kPartChunkMax, ++local)
-          chunks.push_back({i, local, s0, std::min<uint64_t>(kPartChunkMax, n - s0)});
+        for (uint64_t s0 = 0; s0 < n; s0 += kBatchChunk, ++local)
+          chunks.push_back({i, local, s0, std::min<uint64_t>(kBatchChunk, n - s0)});
         for (uint32_t j = 0; j < nb; ++j) bin_table.push_back(i);
         key_off += n;
         hist_off += (uint64_t)local * nb;

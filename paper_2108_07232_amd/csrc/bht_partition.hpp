@@ -68,7 +68,17 @@ constexpr bool kScatterStageDigits = BHT_SCATTER_STAGE_DIGITS != 0; // digits st
 constexpr int kPartBlock = 256;                        // threads per scan block
 constexpr int kPassBlock = BHT_PASS_BLOCK;
 constexpr int kPartSub = BHT_PASS_PER * kPassBlock;   // pairs per sub-tile (4-byte words)
-constexpr uint32_t kPartChunkMax = 4 * kPartSub;       // pairs per partition block, at most
+// Pairs per partition block of one table's build, at most: 128 K (at 2^28
+// pairs, 2,048 first-pass chunks; a line-writing pass pads each (chunk,
+// digit) range, so larger chunks pad less: 1.7% and 3.2% of the pairs at
+// 2^28 against 3.4% and 6.3% with 64 K chunks, and the padded first pass
+// fits the slot array up to LF 0.96 at 2^28 pairs, 0.98 at 2^27); the
+// batched build keeps 64 K-pair chunks.
+#ifndef BHT_PART_CHUNK_SUBS
+#define BHT_PART_CHUNK_SUBS 8
+#endif
+constexpr uint32_t kPartChunkMax = BHT_PART_CHUNK_SUBS * kPartSub;
+constexpr uint32_t kBatchChunk = 4 * kPartSub;
 constexpr uint32_t kMaxFan = 1024;                     // digits of the first pass, at most
 constexpr uint32_t kFan2 = 256;                        // digits of the second pass
 constexpr int kLineSub = 8 * kPassBlock;               // pairs per sub-tile of the line-writing scatter
@@ -351,8 +361,10 @@ __global__ __launch_bounds__(kPartBlock) void part_scan1_kernel(PartPlan P, Part
 constexpr uint64_t kLinePadPerChunk2 = (uint64_t)kFan2 * (kLineWords - 1);
 
 // Second-pass totals -> bin ranges.  One block per first-pass range.  The
-// range's output starts where its input does, shifted, when the pass
-// writes lines, by the most padding the earlier ranges' chunks can add.
+// range's output starts where its input does; when the pass writes lines,
+// rounded up to a whole line (the first pass may not have padded) and
+// shifted by a line per earlier range and by the most padding the earlier
+// ranges' chunks can add, so ranges never overlap.
 __global__ __launch_bounds__(kPartBlock) void part_scan2_kernel(PartPlan P, PartMeta M,
                                                                 uint32_t* __restrict__ status) {
   __shared__ unsigned long long wt[kPartBlock / 64];
@@ -364,8 +376,11 @@ __global__ __launch_bounds__(kPartBlock) void part_scan2_kernel(PartPlan P, Part
   if (threadIdx.x == 0 && words)
     atomicAdd(reinterpret_cast<unsigned long long*>(status + kStatusPass2Words), words);
   const uint32_t d = threadIdx.x;          // kPartBlock == kFan2
-  const unsigned long long shift = P.lines2 ? kLinePadPerChunk2 * M.chunk_first[s] : 0ull;
-  const unsigned long long pos = M.seg_start[s] + shift + base[d];
+  const unsigned long long start =
+      P.lines2 ? (M.seg_start[s] + kLineWords - 1) / kLineWords * kLineWords +
+                     (unsigned long long)kLineWords * s + kLinePadPerChunk2 * M.chunk_first[s]
+               : M.seg_start[s];
+  const unsigned long long pos = start + base[d];
   M.cursor2[(uint64_t)s * kFan2 + d] = pos;
   const uint64_t bin = (uint64_t)s * kFan2 + d;
   if (bin < P.nbins) {
@@ -387,7 +402,8 @@ __device__ __forceinline__ void scatter_range(const T* __restrict__ in_k,
                                               uint64_t end, uint32_t fan, DigitFn digit,
                                               const uint32_t* __restrict__ hrow,
                                               unsigned long long* __restrict__ cur,
-                                              T* __restrict__ out_k, T* __restrict__ out_v) {
+                                              T* __restrict__ out_k, T* __restrict__ out_v,
+                                              bool padded = false) {
   constexpr int SUB = sub_tile<T>();
   constexpr int PER = SUB / kPassBlock;
   __shared__ T sk[SUB];
@@ -436,28 +452,31 @@ __device__ __forceinline__ void scatter_range(const T* __restrict__ in_k,
     // rank within the digit (< 2^14) and digit (< 2^10) share a register
     static_assert(SUB <= (1 << 22) && kMaxFan <= 1024, "rank and digit packing");
     const uint32_t count = len - sub < (uint32_t)SUB ? len - sub : (uint32_t)SUB;
-    // One body, instantiated for a full sub-tile (no per-pair guards, so
-    // the compiler can issue a thread's LDS accesses back to back instead of
-    // one guarded block at a time) and for a partial one; and for digits
-    // staged in LDS or recomputed.  Both choices are uniform over the block.
+    // One body, instantiated for a full sub-tile without padding (no
+    // per-pair guards, so the compiler can issue a thread's LDS accesses
+    // back to back instead of one guarded block at a time) and for the
+    // rest; and for digits staged in LDS or recomputed.  Both choices are
+    // uniform over the block.  With padded input, empty keys are padding of
+    // a line-writing pass: not ranked, not written.
     auto body = [&](auto full_tag, auto staged_tag) {
       constexpr bool FULL = decltype(full_tag)::value;
       constexpr bool STAGED = decltype(staged_tag)::value;
-      uint32_t rd[PER];
+      uint32_t rd[PER];   // ~0: no pair
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const uint32_t i = j * kPassBlock + threadIdx.x;
-        if (FULL || i < count) {
+        rd[j] = ~0u;
+        if (FULL || (i < count && !(padded && reserved_key(k[j])))) {
           const uint32_t d = digit(k[j]);
           rd[j] = (atomicAdd(&cnt[d], 1u) << 10) | d;
         }
       }
       __syncthreads();
-      block_exclusive_scan<kPassBlock, uint32_t>(cnt, start, fan, wt);
+      // staged pairs of this sub-tile (count, less any padding)
+      const uint32_t staged_n = block_exclusive_scan<kPassBlock, uint32_t>(cnt, start, fan, wt);
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
-        const uint32_t i = j * kPassBlock + threadIdx.x;
-        if (FULL || i < count) {
+        if (FULL || rd[j] != ~0u) {
           const uint32_t d = rd[j] & 1023u;
           const uint32_t pos = start[d] + (rd[j] >> 10);
           sk[pos] = k[j];
@@ -482,7 +501,7 @@ __device__ __forceinline__ void scatter_range(const T* __restrict__ in_k,
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const uint32_t i = j * kPassBlock + threadIdx.x;
-        if (FULL || i < count) {
+        if (FULL || i < staged_n) {
           const T key = sk[i];
           const uint32_t d = STAGED ? (uint32_t)sd[i] : digit(key);
           const uint32_t dst = start[d] + i;
@@ -493,11 +512,12 @@ __device__ __forceinline__ void scatter_range(const T* __restrict__ in_k,
     };
     using yes = std::integral_constant<bool, true>;
     using no = std::integral_constant<bool, false>;
+    const bool full = count == (uint32_t)SUB && !padded;
     if (staged) {
-      if (count == (uint32_t)SUB) body(yes(), yes());
+      if (full) body(yes(), yes());
       else body(no(), yes());
     } else {
-      if (count == (uint32_t)SUB) body(yes(), no());
+      if (full) body(yes(), no());
       else body(no(), no());
     }
 #pragma unroll
@@ -518,7 +538,8 @@ __global__ __launch_bounds__(kPassBlock, kScatterBlocksPerCU) void part_scatter_
   const PartPlan& P = p.P;
   const uint32_t level = p.level;
   scatter_range(p.in_k, p.in_v, begin, end, p.fan,
-                [&](T k) { return part_digit(P, level, k); }, h, cur, p.out_k, p.out_v);
+                [&](T k) { return part_digit(P, level, k); }, h, cur, p.out_k, p.out_v,
+                p.padded != 0);
 }
 
 // Per-digit line counts packed beside the digit counts, for one scan: the
@@ -726,8 +747,10 @@ __device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
   constexpr int S = bin_slots<B>();
   constexpr int RMAX = S / B;                    // buckets per bin, at most
   __shared__ u64x2 tbl2[S / 2];
-  __shared__ uint32_t load[RMAX + 1];            // [RMAX]: target of lanes without a pair
-  __shared__ unsigned long long spill;           // target of the stores of those lanes
+  // [RMAX + lane]: counter of a lane without a pair (one per lane, so a
+  // wave's idle lanes do not serialize on one address)
+  __shared__ uint32_t load[RMAX + 64];
+  __shared__ unsigned long long spill[64];       // target of the stores of those lanes
   __shared__ uint32_t ovf;
   unsigned long long* tbl = reinterpret_cast<unsigned long long*>(tbl2);
   const u64x2 e2 = {kEmptyPair, kEmptyPair};
@@ -756,10 +779,11 @@ __device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
     for (int j = 0; j < kBinPer; ++j) {
       full[j] = ~0u;
       const uint32_t i = r0 + j * kBinBlock + threadIdx.x;
-      // No branch per pair: a lane without a pair (past the bin's end)
-      // counts on a spare counter and stores to a spare word, so the
-      // claims of a thread's pairs issue back to back.  lb < nb by
-      // construction of the partition; otherwise the build fails.
+      // No branch per pair: a lane without a pair (past the bin's end, or
+      // padding) counts on a spare counter and stores to a spare word of
+      // its own, so the claims of a thread's pairs issue back to back.
+      // lb < nb by construction of the partition; otherwise the build
+      // fails.
       const uint32_t lb = hash32(H, 0, k[j]) - (uint32_t)first;
       // the empty key marks padding of a line-writing pass (a caller's
       // empty key has already failed the build)
@@ -767,9 +791,9 @@ __device__ __forceinline__ uint32_t place_bin(uint64_t* __restrict__ slots,
       const bool inside = lb < nb;
       if (valid && !inside) flags |= kFlagFailed;
       const bool claim = valid && inside;
-      const uint32_t s = atomicAdd(&load[claim ? lb : (uint32_t)RMAX], 1u);
+      const uint32_t s = atomicAdd(&load[claim ? lb : (uint32_t)RMAX + __lane_id()], 1u);
       const bool placed = claim && s < cap;
-      unsigned long long* dst = placed ? &tbl[lb * B + s] : &spill;
+      unsigned long long* dst = placed ? &tbl[lb * B + s] : &spill[__lane_id()];
       *dst = ((unsigned long long)v[j] << 32) | k[j];
       if (claim && !placed) full[j] = lb;
     }

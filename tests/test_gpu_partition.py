@@ -79,12 +79,13 @@ def test_partitioned_build_invariants_and_find(scheme, b, tile, n, lf):
     t.close()
 
 
-@pytest.mark.parametrize("scheme,b,n,lf", [
-    ("bcht", 16, 9_000_011, 0.9),         # two passes: 1,221 bins of 512 buckets
-    ("bcht", 32, 8_000_000, 0.9),
-    ("cht1", 1, 4_000_037, 0.8),          # two passes: 1,221 bins of 4,096 slots
+@pytest.mark.parametrize("scheme,b,n,lf,padded", [
+    ("bcht", 16, 9_000_011, 0.9, (True, False)),   # two passes: 1,221 bins of 512 buckets
+    ("bcht", 32, 8_000_000, 0.9, (True, False)),
+    ("cht1", 1, 4_000_037, 0.8, (True, False)),    # two passes: 1,221 bins of 4,096 slots
+    ("bcht", 16, 1 << 25, 0.9, (True, True)),      # 4,552 bins, 64 K-pair chunks
 ])
-def test_partitioned_build_two_passes(scheme, b, n, lf):
+def test_partitioned_build_two_passes(scheme, b, n, lf, padded):
     print("partitioned two-pass %s b=%d n=%d lf=%g" % (scheme, b, n, lf), flush=True)
     keys, vals = workload(n, 12)
     params = oracle.params_for(scheme, n, lf, 600, b=b)
@@ -92,25 +93,30 @@ def test_partitioned_build_two_passes(scheme, b, n, lf):
     t, st = build_partitioned(params, keys, vals)
     assert st == bht().BHT_OK, bht().bht_status_string(st)
     check_table(t, params, keys, vals, n_queries=1 << 21)
-    # both passes (at most 256 digits each) pad their ranges to whole
-    # 128-byte lines: each pass writes a multiple of 32 words, less than a
-    # line more per (chunk, digit) range
-    pad1, pad2 = bht().bht_build_padding(t.handle)
+    # a pass of at most 256 digits pads its ranges to whole 128-byte lines
+    # unless that padding would be heavy (small chunks): it then writes a
+    # multiple of 32 words, less than a line more per (chunk, digit) range
+    pads = bht().bht_build_padding(t.handle)
     ranges = -(-n // 16384) * 256
-    for pad in (pad1, pad2):
-        assert 0 < pad <= 31 * ranges and (n + pad) % 32 == 0
+    for pad, on in zip(pads, padded):
+        if on:
+            assert 0 < pad <= 31 * ranges and (n + pad) % 32 == 0
+        else:
+            assert pad == 0
     t.close()
 
 
 def test_partitioned_first_pass_unpadded_when_slots_are_short():
-    """At 2^26 pairs and LF 0.985 the padded first-pass output could exceed
-    the slot array it is written to, so only the second pass pads; the
-    layout is valid and lookups equal brute force."""
+    """At 2^27 pairs and LF 0.99 the padded first-pass output could exceed
+    the slot array it is written to (up to 2.1 M padding pairs, 1.4 M spare
+    slots), so only the second pass pads; the layout is valid and lookups
+    equal brute force.  (Near its load limit the build runs with an
+    eviction cap of 1024.)"""
     B = bht()
-    n = 1 << 26
+    n = 1 << 27
     keys, vals = workload(n, 13)
     for s in range(4):
-        params = oracle.params_for("bcht", n, 0.985, 620 + s)
+        params = oracle.params_for("bcht", n, 0.99, 620 + s, max_chain=1024)
         t, st = build_partitioned(params, keys, vals)
         if st == B.BHT_OK:
             break
