@@ -519,7 +519,7 @@ bool part_plan(const bht_table* t, uint64_t n, PartPlan* P) {
 // mid_words: words of each first-pass output array (of two passes; keys,
 // then values, in the slot array); keys/vals hold out_words words each.
 struct PartLayout {
-  uint64_t hist1, hist2, total1, cursor1, seg_start, seg_len, chunk_first, total2, cursor2,
+  uint64_t hist1, hist2, total1, cursor1, seg_start, seg_len, chunk_first, chunk_seg, total2, cursor2,
       bin_start, bin_len, ovf_len, head, keys, vals, bytes;
   uint64_t chunks1, chunks2, mid_words, out_words;
 };
@@ -545,6 +545,7 @@ PartLayout part_layout(const PartPlan& P, uint64_t n, uint32_t word_bytes = 4) {
   L.seg_start = take(P.fan1 * 8ull);
   L.seg_len = take(P.fan1 * 8ull);
   L.chunk_first = take((P.fan1 + 1) * 4ull);
+  L.chunk_seg = take(L.chunks2 * 4ull);
   L.total2 = take(P.levels == 2 ? P.fan1 * (uint64_t)kFan2 * 8 : 0);
   L.cursor2 = take(P.levels == 2 ? P.fan1 * (uint64_t)kFan2 * 8 : 0);
   L.bin_start = take(P.nbins * 8ull);
@@ -612,6 +613,7 @@ PartMeta part_meta(const PartLayout& L, char* w) {
   M.seg_start = reinterpret_cast<unsigned long long*>(w + L.seg_start);
   M.seg_len = reinterpret_cast<unsigned long long*>(w + L.seg_len);
   M.chunk_first = reinterpret_cast<uint32_t*>(w + L.chunk_first);
+  M.chunk_seg = reinterpret_cast<uint32_t*>(w + L.chunk_seg);
   M.total2 = reinterpret_cast<unsigned long long*>(w + L.total2);
   M.cursor2 = reinterpret_cast<unsigned long long*>(w + L.cursor2);
   M.bin_start = reinterpret_cast<unsigned long long*>(w + L.bin_start);

@@ -118,6 +118,7 @@ struct PartMeta {
   unsigned long long* seg_start; // [fan1]  first-pass digit ranges
   unsigned long long* seg_len;   // [fan1]
   uint32_t* chunk_first;         // [fan1 + 1] second-pass chunks per range, prefix
+  uint32_t* chunk_seg;           // [second-pass chunks] the range of each chunk
   unsigned long long* total2;    // [fan1 * 256]
   unsigned long long* cursor2;   // [fan1 * 256]
   unsigned long long* bin_start; // [nbins]
@@ -175,12 +176,7 @@ __device__ __forceinline__ bool part_chunk(const PartPassT<T>& p, uint32_t blk, 
   }
   const uint32_t* cf = p.M.chunk_first;
   if (blk >= cf[p.P.fan1]) return false;
-  uint32_t lo = 0, hi = p.P.fan1;          // cf[lo] <= blk < cf[hi]
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (cf[mid] <= blk) lo = mid;
-    else hi = mid;
-  }
+  const uint32_t lo = p.M.chunk_seg[blk];  // cf[lo] <= blk < cf[lo + 1]
   const uint64_t s0 = p.M.seg_start[lo], s1 = s0 + p.M.seg_len[lo];
   const uint64_t b = s0 + (uint64_t)(blk - cf[lo]) * C;
   *seg = lo;
@@ -353,7 +349,10 @@ __global__ __launch_bounds__(kPartBlock) void part_scan1_kernel(PartPlan P, Part
   __syncthreads();
   const unsigned long long total =
       block_exclusive_scan<kPartBlock, unsigned long long>(chunks, base, P.fan1, wt);
-  for (uint32_t d = threadIdx.x; d < P.fan1; d += kPartBlock) M.chunk_first[d] = (uint32_t)base[d];
+  for (uint32_t d = threadIdx.x; d < P.fan1; d += kPartBlock) {
+    M.chunk_first[d] = (uint32_t)base[d];
+    for (uint64_t c = base[d]; c < base[d] + chunks[d]; ++c) M.chunk_seg[c] = d;
+  }
   if (threadIdx.x == 0) M.chunk_first[P.fan1] = (uint32_t)total;
 }
 
