@@ -541,18 +541,22 @@ __global__ __launch_bounds__(kPassBlock, kScatterBlocksPerCU) void part_scatter_
                 p.padded != 0);
 }
 
-// Per-digit line counts packed beside the digit counts, for one scan: the
-// digit's new pairs (< 2^16) in the low half, the whole lines it writes in
-// this sub-tile in the high half (all pairs and pending words when the
-// sub-tile ends the range, else only the full lines).
+// Per-digit work items packed beside the digit counts, for one scan: the
+// digit's new pairs (< 2^16) in the low half, its items in the high half.
+// An item is a whole line to write (all pairs and carried words when the
+// sub-tile ends the range, else only the full lines); a digit with pairs
+// but no full line gets one item that only carries them.
 struct LinePack {
   const uint32_t* cnt;
   const uint32_t* carry;
   bool last;
-  __device__ __forceinline__ uint32_t operator[](uint32_t d) const {
+  __device__ __forceinline__ uint32_t lines(uint32_t d) const {
     const uint32_t tot = carry[d] + cnt[d];
-    const uint32_t lines = last ? (tot + kLineWords - 1) / kLineWords : tot / kLineWords;
-    return (lines << 16) | cnt[d];
+    return last ? (tot + kLineWords - 1) / kLineWords : tot / kLineWords;
+  }
+  __device__ __forceinline__ uint32_t operator[](uint32_t d) const {
+    const uint32_t n = lines(d);
+    return ((n ? n : (cnt[d] ? 1u : 0u)) << 16) | cnt[d];
   }
 };
 
@@ -563,7 +567,9 @@ struct LinePack {
 // output then continues with the words carried from the previous sub-tile
 // followed by its staged pairs, and only the lines that are full are
 // written (half a wave per line, from a descriptor built per line); the
-// remainder (< 32 words) is carried in LDS.  The range's last sub-tile
+// remainder (< 32 words) is carried in LDS, copied there by the digit's
+// first item after it has read the words carried before.  The range's last
+// sub-tile
 // writes the remainder too, padded with the empty key and value 0.  With
 // padded input, empty keys are padding and skipped.  Partial lines, each
 // written twice from different times or different workgroups, are what
@@ -581,7 +587,8 @@ __device__ __forceinline__ void scatter_lines_range(const uint32_t* __restrict__
   constexpr int PER = SUB / kPassBlock;
   constexpr uint32_t LW = kLineWords;
   constexpr uint32_t FMAX = kLineMaxFan;
-  // lines of one sub-tile, at most: every word once, plus a partial line per digit
+  // items of one sub-tile, at most: every word once, plus a partial line
+  // (or a carry-only item) per digit
   constexpr int MAXLINES = (SUB + FMAX * (LW - 1)) / LW + FMAX;
   static_assert(SUB < (1 << 16) && MAXLINES < (1 << 16), "packed scan fields");
   static_assert(kPassBlock % LW == 0, "half waves per block");
@@ -592,9 +599,14 @@ __device__ __forceinline__ void scatter_lines_range(const uint32_t* __restrict__
   __shared__ uint32_t pre[FMAX];          // packed exclusive prefix (first line, first staged pair)
   __shared__ uint32_t carry[FMAX];        // carried words per digit
   __shared__ uint32_t run[FMAX];          // next output position per digit (line-aligned)
-  // per line: output position; index (into skv) of the staged pair for
-  // lane 0; index of the carried word for lane 0; lanes below .w & 63 take
-  // carried words, lanes from .w >> 8 on write padding
+  // per item: .x output position of its line; .y index (into skv) of the
+  // staged pair for lane 0; .z bits 0-14 index of the carried pair for
+  // lane 0, bits 15-28 the staged index of the first pair to carry on;
+  // .w bits 0-5 lanes taking carried pairs, 8-13 lanes taking carried or
+  // staged pairs (the rest write padding), 16-21 pairs to carry on, 24-28
+  // their offset in the digit's carry slots, bit 31 set when the item
+  // writes a line
+  static_assert(SUB + FMAX * LW < (1 << 15) && SUB < (1 << 14), "item fields");
   __shared__ uint4 line_desc[MAXLINES];
   __shared__ uint32_t wt[kPassBlock / 64];
   const uint32_t tid = threadIdx.x, hl = tid / LW, l = tid % LW;
@@ -649,45 +661,52 @@ __device__ __forceinline__ void scatter_lines_range(const uint32_t* __restrict__
         skv[pos] = make_uint2(k[j], v[j]);
       }
     }
+    // items of each digit; then the digit's output advances by the lines
+    // written, its carry count becomes the new one and its pair count
+    // clears (the items hold everything the write-out needs)
     for (uint32_t d = tid; d < fan; d += kPassBlock) {
+      const LinePack lp{cnt, carry, last};
       const uint32_t p = pre[d], cf = carry[d], c = cnt[d];
-      const uint32_t first = p >> 16;
-      const uint32_t lines = (LinePack{cnt, carry, last}[d]) >> 16;
-      for (uint32_t q = 0; q < lines; ++q) {
+      const uint32_t first = p >> 16, p_low = p & 0xFFFFu;
+      const uint32_t lines = lp.lines(d), tot = cf + c;
+      // pairs carried on: those past the last whole line, all staged when
+      // a line is written, else appended after the carried ones
+      const uint32_t nc_new = last ? 0u : tot - lines * LW;
+      const uint32_t t_src = lines ? p_low + lines * LW - cf : p_low;
+      const uint32_t t_off = lines ? 0u : cf;
+      const uint32_t t_cnt = lines ? nc_new : c;
+      const uint32_t items = lines ? lines : (c ? 1u : 0u);
+      for (uint32_t q = 0; q < items; ++q) {
         // words of this line: e = q * LW + lane over [carried, staged, padding)
         const uint32_t e0 = q * LW;
         const uint32_t nc = cf > e0 ? cf - e0 : 0u;                 // carried lanes
         const uint32_t nw = cf + c > e0 ? min(cf + c - e0, LW) : 0u; // carried + staged lanes
-        line_desc[first + q] = make_uint4(run[d] + e0, (p & 0xFFFFu) + e0 - cf,
-                                          SUB + d * LW + e0, nc | (nw << 8));
+        const uint32_t carry_on = q == 0 ? (t_cnt << 16) | (t_off << 24) : 0u;
+        line_desc[first + q] =
+            make_uint4(run[d] + e0, p_low + e0 - cf, (SUB + d * LW) | (t_src << 15),
+                       nc | (nw << 8) | carry_on | (lines ? 0x80000000u : 0u));
       }
+      run[d] += lines * LW;
+      carry[d] = nc_new;
+      cnt[d] = 0;
     }
     __syncthreads();
-    // whole lines: carried words first, then the staged pairs, then padding
-    const uint32_t nlines = total >> 16;
-    for (uint32_t it = hl; it < nlines; it += kPassBlock / LW) {
+    // whole lines: carried pairs first, then the staged pairs, then
+    // padding; the digit's first item then carries its remainder on (the
+    // staging is only read here, and only this item touches the digit's
+    // carry slots)
+    const uint32_t nitems = total >> 16;
+    for (uint32_t it = hl; it < nitems; it += kPassBlock / LW) {
       const uint4 ld = line_desc[it];
-      uint2 kv = make_uint2(kEmptyKey, 0u);
-      if (l < (ld.w >> 8)) kv = skv[l < (ld.w & 63u) ? ld.z + l : ld.y + l];
-      out_k[ld.x + l] = kv.x;
-      out_v[ld.x + l] = kv.y;
-    }
-    __syncthreads();
-    // carry what does not fill a line (half a wave per digit); the digit's
-    // output advances by the lines written and its count clears
-    for (uint32_t d = hl; d < fan; d += kPassBlock / LW) {
-      const uint32_t cf = carry[d], c = cnt[d], tot = cf + c;
-      const uint32_t lines = last ? (tot + LW - 1) / LW : tot / LW;
-      const uint32_t nc = last ? 0u : tot - lines * LW;
-      const uint32_t e = lines * LW + l;
-      if (l < nc && e >= cf) {
-        skv[SUB + d * LW + l] = skv[(pre[d] & 0xFFFFu) + e - cf];
+      const uint32_t cbase = ld.z & 0x7FFFu;
+      if (ld.w >> 31) {
+        uint2 kv = make_uint2(kEmptyKey, 0u);
+        if (l < ((ld.w >> 8) & 63u)) kv = skv[l < (ld.w & 63u) ? cbase + l : ld.y + l];
+        out_k[ld.x + l] = kv.x;
+        out_v[ld.x + l] = kv.y;
       }
-      if (l == 0) {
-        run[d] += lines * LW;
-        carry[d] = nc;
-        cnt[d] = 0;
-      }
+      if (l < ((ld.w >> 16) & 63u))
+        skv[cbase + ((ld.w >> 24) & 31u) + l] = skv[(ld.z >> 15) + l];
     }
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
