@@ -292,7 +292,7 @@ bht_status bht_get_probe_stats(const bht_table* t, uint64_t* build_probes, uint6
  * their chains continue concurrently, as in the concurrent build, and
  * since no bucket ever loses a pair the layout obeys the same invariants
  * (every key in a candidate bucket, the early-exit property).  It allocates a
- * library-owned workspace of about 8 bytes per pair on first use (kept
+ * library-owned workspace of about 8-9 bytes per pair on first use (kept
  * until bht_destroy).  Iceberg tables (Section III-C) take the same path
  * with primaries filled on chip up to iht_threshold pairs and the rest
  * inserted at their secondary choices afterwards, concurrently (a pair
