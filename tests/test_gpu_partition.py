@@ -171,6 +171,28 @@ def test_bin_with_more_pairs_than_one_placement_round():
     t.close()
 
 
+def test_line_writing_passes_with_skewed_digits():
+    """2^25 pairs whose first buckets all lie in the first quarter of a
+    table of 2^27 slots (16 of the first pass's 64 digits, 512 pairs per
+    digit and sub-tile, 16 lines per digit): both radix passes write whole
+    lines, carry remainders and pad, and the layout is valid with lookups
+    equal to brute force."""
+    B = bht()
+    n = 1 << 25
+    params = oracle.params_for("bcht", n, 0.25, 640)
+    keys = datagen.unique_keys(5 * n, 41)
+    h0 = oracle.hash32_many(params.a[0], params.c[0], keys, params.m)
+    keys = keys[h0 < params.m // 4][:n]
+    assert len(keys) == n
+    vals = datagen.values(n, 41)
+    t, st = build_partitioned(params, keys, vals)
+    assert st == B.BHT_OK, B.bht_status_string(st)
+    pad1, pad2 = B.bht_build_padding(t.handle)
+    assert pad1 > 0 and pad2 > 0 and (n + pad1) % 32 == 0 and (n + pad2) % 32 == 0
+    check_table(t, params, keys, vals, n_queries=1 << 21)
+    t.close()
+
+
 def test_repeated_builds_reuse_the_workspace():
     """Rebuilding a table (larger, then smaller inputs) gives a fresh valid
     layout each time."""
