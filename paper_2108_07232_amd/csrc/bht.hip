@@ -447,10 +447,11 @@ bool part_kernels(const bht_table* t, uint32_t w, PartKernels* k) {
   return false;
 }
 
-// Padding words a line-writing pass over `chunks` chunks of `fan` digits
-// adds to n pairs, at most: under a line per non-empty (chunk, digit) range.
-uint64_t line_pad_bound(uint64_t chunks, uint64_t fan, uint64_t n) {
-  return std::min<uint64_t>(chunks * fan, n) * (kLineWords - 1);
+// Padding pairs a line-writing pass over `chunks` chunks of `fan` digits
+// adds to n pairs, at most: under a line (lw pairs) per non-empty (chunk,
+// digit) range.
+uint64_t line_pad_bound(uint64_t chunks, uint64_t fan, uint64_t n, uint64_t lw = kLineWords) {
+  return std::min<uint64_t>(chunks * fan, n) * (lw - 1);
 }
 
 uint64_t round_to_line(uint64_t words) { return (words + kLineWords - 1) / kLineWords * kLineWords; }
@@ -487,19 +488,20 @@ bool part_plan(const bht_table* t, uint64_t n, PartPlan* P) {
     if (fan1 > kMaxFan) return false;
     P->fan1 = (uint32_t)fan1;
   }
-  // Passes of at most 256 digits over 32-bit pairs write whole lines, while
-  // the padding they add is expected to stay under 8% of the pairs (half a
-  // line per (chunk, digit) range; small tables have small chunks), the
+  // Passes of at most 256 digits write whole lines, while the padding they
+  // add is expected to stay under 8% of the pairs (half a line per (chunk,
+  // digit) range; small tables have small chunks), the
   // positions, padding included, stay below 2^32, and (two passes) the
   // padded first-pass output still fits the slot array it is written to.
   // At 2^24 pairs a padded second pass (12% padding) is no faster than the
   // plain scatter; at 2^25 (6%) it is 8% faster.
-  if (kScatterLines && t->key_bits == 32) {
-    auto light = [n](uint64_t chunks, uint64_t fan) {
-      return line_pad_bound(chunks, fan, n) <= n * 16 / 100;
+  if (kScatterLines) {
+    const uint64_t lw = t->key_bits == 64 ? line_words<uint64_t>() : line_words<uint32_t>();
+    auto light = [n, lw](uint64_t chunks, uint64_t fan) {
+      return line_pad_bound(chunks, fan, n, lw) <= n * 16 / 100;
     };
     const uint64_t chunks1 = (n + P->chunk - 1) / P->chunk;
-    const uint64_t in2 = n + line_pad_bound(chunks1, P->fan1, n);
+    const uint64_t in2 = n + line_pad_bound(chunks1, P->fan1, n, lw);
     if (P->levels == 1) {
       P->lines1 = P->fan1 <= kLineMaxFan && light(chunks1, P->fan1) && in2 < (1ull << 32);
     } else {
@@ -534,7 +536,8 @@ PartLayout part_layout(const PartPlan& P, uint64_t n, uint32_t word_bytes = 4) {
   };
   L.chunks1 = (n + P.chunk - 1) / P.chunk;
   // first-pass output words, padding included
-  const uint64_t in2 = n + (P.lines1 ? line_pad_bound(L.chunks1, P.fan1, n) : 0);
+  const uint64_t in2 =
+      n + (P.lines1 ? line_pad_bound(L.chunks1, P.fan1, n, 128 / word_bytes) : 0);
   L.chunks2 = P.levels == 2 ? in2 / P.chunk + P.fan1 : 0;
   L.mid_words = P.levels == 2 ? (P.lines1 ? round_to_line(in2) : n) : 0;
   L.out_words = in2 + (P.lines2 ? L.chunks2 * kLinePadPerChunk2 + kLineWords * (P.fan1 + 1) : 0);
@@ -636,10 +639,11 @@ void launch_radix(const PartPlan& P, const PartMeta& M, const PartLayout& L, con
   if constexpr (sizeof(T) == 4) {
     hist = part_hist_kernel<uint32_t>;
     scatter = part_scatter_kernel<uint32_t>;
-    scatter_lines = part_scatter_lines_kernel;
+    scatter_lines = part_scatter_lines_kernel<uint32_t>;
   } else {
     hist = part_hist64_kernel;
     scatter = part_scatter64_kernel;
+    scatter_lines = part_scatter_lines_kernel<uint64_t>;
   }
   part_clear_kernel<<<64, kPartBlock, 0, st>>>(M, P.fan1, P.levels, status);
   PartPassT<T> p1;
@@ -687,9 +691,10 @@ bht_status build64_partitioned(bht_table* t, const uint64_t* keys, const uint64_
   const PartMeta M = part_meta(L, w);
   uint64_t* keys2 = reinterpret_cast<uint64_t*>(w + L.keys);
   uint64_t* vals2 = reinterpret_cast<uint64_t*>(w + L.vals);
-  // the first of two passes writes into the slot array (2 words per slot)
+  // the first of two passes writes into the slot array (2 words per slot,
+  // at least mid_words pairs: the plan checks it when the pass pads)
   uint64_t* mid_k = t->d_slots;
-  uint64_t* mid_v = mid_k + n;
+  uint64_t* mid_v = mid_k + L.mid_words;
 
   if (t->timing) HIP_TRY(hipEventRecord(t->ev[0], st));
   launch_radix<uint64_t>(P, M, L, keys, vals, n, mid_k, mid_v, keys2, vals2, t->d_status, st);

@@ -104,9 +104,12 @@ struct PartPlan {
   uint32_t lines2;      // the same for the second pass
 };
 
-// Words of a (chunk, digit) range of c pairs when a pass writes whole lines.
-__host__ __device__ __forceinline__ uint32_t line_pad(uint32_t c) {
-  return (c + kLineWords - 1) & ~(kLineWords - 1);
+// Words of T per 128-byte line, and the words of a (chunk, digit) range of
+// c pairs when a pass writes whole lines of lw words.
+template <typename T>
+constexpr uint32_t line_words() { return 128 / sizeof(T); }
+__host__ __device__ __forceinline__ uint32_t line_pad(uint32_t c, uint32_t lw = kLineWords) {
+  return (c + lw - 1) & ~(lw - 1);
 }
 
 // Device metadata of one partitioned build (one allocation, see the host).
@@ -248,16 +251,16 @@ template <typename T>
 constexpr int sub_tile() { return sizeof(T) == 4 ? kPartSub : kPartSub / 2; }
 
 // Digit counts of the pairs [begin, end) of in_k: stored in hrow (for the
-// scatter's reservations) and added to tot, rounded up to whole lines when
-// the scatter writes lines (pad_totals); returns whether the range held a
-// reserved key.  With skip_pads, empty keys are padding and not counted.
-// Every thread of the block calls it.
+// scatter's reservations) and added to tot, rounded up to whole lines of
+// pad_to words when the scatter writes lines (pad_to = 0: not rounded);
+// returns whether the range held a reserved key.  With skip_pads, empty
+// keys are padding and not counted.  Every thread of the block calls it.
 template <typename T, typename DigitFn>
 __device__ __forceinline__ bool hist_range(const T* __restrict__ in_k, uint64_t begin,
                                            uint64_t end, uint32_t fan, DigitFn digit,
                                            uint32_t* __restrict__ hrow,
                                            unsigned long long* __restrict__ tot,
-                                           bool skip_pads = false, bool pad_totals = false) {
+                                           bool skip_pads = false, uint32_t pad_to = 0) {
   __shared__ uint32_t cnt[kMaxFan];
   for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) cnt[d] = 0;
   __syncthreads();
@@ -295,7 +298,7 @@ __device__ __forceinline__ bool hist_range(const T* __restrict__ in_k, uint64_t 
   for (uint32_t d = threadIdx.x; d < fan; d += kPassBlock) {
     const uint32_t c = cnt[d];
     hrow[d] = c;
-    if (c) atomicAdd(&tot[d], (unsigned long long)(pad_totals ? line_pad(c) : c));
+    if (c) atomicAdd(&tot[d], (unsigned long long)(pad_to ? line_pad(c, pad_to) : c));
   }
   return sentinel;
 }
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(kPassBlock) void part_hist_kernel(PartPassT<T> p) {
   const uint32_t level = p.level;
   const bool sentinel = hist_range(p.in_k, begin, end, p.fan,
                                    [&](T k) { return part_digit(P, level, k); }, h, tot,
-                                   p.padded != 0, p.lines != 0);
+                                   p.padded != 0, p.lines ? line_words<T>() : 0u);
   if (level == 1 && sentinel) atomicOr(p.status, kFlagSentinel);
 }
 
@@ -546,13 +549,14 @@ __global__ __launch_bounds__(kPassBlock, kScatterBlocksPerCU) void part_scatter_
 // An item is a whole line to write (all pairs and carried words when the
 // sub-tile ends the range, else only the full lines); a digit with pairs
 // but no full line gets one item that only carries them.
+template <uint32_t LW>
 struct LinePack {
   const uint32_t* cnt;
   const uint32_t* carry;
   bool last;
   __device__ __forceinline__ uint32_t lines(uint32_t d) const {
     const uint32_t tot = carry[d] + cnt[d];
-    return last ? (tot + kLineWords - 1) / kLineWords : tot / kLineWords;
+    return last ? (tot + LW - 1) / LW : tot / LW;
   }
   __device__ __forceinline__ uint32_t operator[](uint32_t d) const {
     const uint32_t n = lines(d);
@@ -560,32 +564,47 @@ struct LinePack {
   }
 };
 
+// Pair staged in LDS by the line-writing scatter, and the padding pair.
+template <typename T> struct LinePair;
+template <> struct LinePair<uint32_t> {
+  using type = uint2;
+  __device__ static uint2 make(uint32_t k, uint32_t v) { return make_uint2(k, v); }
+  __device__ static uint2 pad() { return make_uint2(kEmptyKey, 0u); }
+};
+template <> struct LinePair<uint64_t> {
+  using type = u64x2;
+  __device__ static u64x2 make(uint64_t k, uint64_t v) { return u64x2{k, v}; }
+  __device__ static u64x2 pad() { return u64x2{kEmpty64, 0ull}; }
+};
+
 // scatter_range for at most kLineMaxFan digits that stores whole 128-byte
-// lines only.  Each digit's range of this chunk (hrow[d] pairs) is reserved
-// rounded up to whole lines at a line-aligned cursor.  Per sub-tile the
-// pairs are ranked and staged by digit as in scatter_range; a digit's
-// output then continues with the words carried from the previous sub-tile
-// followed by its staged pairs, and only the lines that are full are
-// written (half a wave per line, from a descriptor built per line); the
-// remainder (< 32 words) is carried in LDS, copied there by the digit's
-// first item after it has read the words carried before.  The range's last
-// sub-tile
-// writes the remainder too, padded with the empty key and value 0.  With
-// padded input, empty keys are padding and skipped.  Partial lines, each
-// written twice from different times or different workgroups, are what
-// slows the plain scatter.  Every thread of the block calls it.
-template <typename DigitFn>
-__device__ __forceinline__ void scatter_lines_range(const uint32_t* __restrict__ in_k,
-                                                    const uint32_t* __restrict__ in_v,
+// lines only (32 pairs of 4-byte words, or 16 of 8-byte words; 8 K or 4 K
+// pairs per sub-tile).  Each digit's range of this chunk (hrow[d] pairs) is
+// reserved rounded up to whole lines at a line-aligned cursor.  Per
+// sub-tile the pairs are ranked and staged by digit as in scatter_range; a
+// digit's output then continues with the pairs carried from the previous
+// sub-tile followed by its staged pairs, and only the lines that are full
+// are written (half a wave or a quarter per line, from a descriptor built
+// per line); the remainder (less than a line) is carried in LDS, copied
+// there by the digit's first item after it has read the pairs carried
+// before.  The range's last sub-tile writes the remainder too, padded with
+// the empty key and value 0.  With padded input, empty keys are padding and
+// skipped.  Partial lines, each written twice from different times or
+// different workgroups, are what slows the plain scatter.  Every thread of
+// the block calls it.
+template <typename T, typename DigitFn>
+__device__ __forceinline__ void scatter_lines_range(const T* __restrict__ in_k,
+                                                    const T* __restrict__ in_v,
                                                     uint64_t begin, uint64_t end, uint32_t fan,
                                                     bool padded, DigitFn digit,
                                                     const uint32_t* __restrict__ hrow,
                                                     unsigned long long* __restrict__ cur,
-                                                    uint32_t* __restrict__ out_k,
-                                                    uint32_t* __restrict__ out_v) {
-  constexpr int SUB = kLineSub;
+                                                    T* __restrict__ out_k,
+                                                    T* __restrict__ out_v) {
+  using Pair = typename LinePair<T>::type;
+  constexpr int SUB = kLineSub * 4 / (int)sizeof(T);
   constexpr int PER = SUB / kPassBlock;
-  constexpr uint32_t LW = kLineWords;
+  constexpr uint32_t LW = line_words<T>();
   constexpr uint32_t FMAX = kLineMaxFan;
   // items of one sub-tile, at most: every word once, plus a partial line
   // (or a carry-only item) per digit
@@ -594,7 +613,7 @@ __device__ __forceinline__ void scatter_lines_range(const uint32_t* __restrict__
   static_assert(kPassBlock % LW == 0, "half waves per block");
   // staged pairs [0, SUB), then LW carried pairs per digit, key and value
   // side by side (one 8-byte LDS access per pair)
-  __shared__ uint2 skv[SUB + FMAX * LW];
+  __shared__ Pair skv[SUB + FMAX * LW];
   __shared__ uint32_t cnt[FMAX];          // new pairs per digit in this sub-tile
   __shared__ uint32_t pre[FMAX];          // packed exclusive prefix (first line, first staged pair)
   __shared__ uint32_t carry[FMAX];        // carried words per digit
@@ -612,15 +631,15 @@ __device__ __forceinline__ void scatter_lines_range(const uint32_t* __restrict__
   const uint32_t tid = threadIdx.x, hl = tid / LW, l = tid % LW;
   for (uint32_t d = tid; d < fan; d += kPassBlock) {
     const uint32_t c = hrow[d];
-    run[d] = c ? (uint32_t)atomicAdd(&cur[d], (unsigned long long)line_pad(c)) : 0u;
+    run[d] = c ? (uint32_t)atomicAdd(&cur[d], (unsigned long long)line_pad(c, LW)) : 0u;
     cnt[d] = 0;
     carry[d] = 0;
   }
-  const uint32_t* __restrict__ kb = in_k + begin;
-  const uint32_t* __restrict__ vb = in_v + begin;
+  const T* __restrict__ kb = in_k + begin;
+  const T* __restrict__ vb = in_v + begin;
   const uint32_t len = (uint32_t)(end - begin);
   const uint32_t last_i = len - 1;
-  uint32_t k[PER], v[PER];
+  T k[PER], v[PER];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const uint32_t o = j * kPassBlock + tid;
@@ -628,7 +647,7 @@ __device__ __forceinline__ void scatter_lines_range(const uint32_t* __restrict__
     v[j] = vb[o < len ? o : last_i];
   }
   for (uint32_t sub = 0; sub < len; sub += SUB) {
-    uint32_t nk[PER], nv[PER];
+    T nk[PER], nv[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       const uint32_t o = sub + SUB + j * kPassBlock + tid;
@@ -645,27 +664,27 @@ __device__ __forceinline__ void scatter_lines_range(const uint32_t* __restrict__
     for (int j = 0; j < PER; ++j) {
       const uint32_t i = j * kPassBlock + tid;
       rd[j] = ~0u;
-      if (i < count && !(padded && k[j] == kEmptyKey)) {
+      if (i < count && !(padded && reserved_key(k[j]))) {
         const uint32_t d = digit(k[j]);
         rd[j] = (atomicAdd(&cnt[d], 1u) << 8) | d;
       }
     }
     __syncthreads();
     const uint32_t total =
-        block_exclusive_scan<kPassBlock, uint32_t>(LinePack{cnt, carry, last}, pre, fan, wt);
+        block_exclusive_scan<kPassBlock, uint32_t>(LinePack<LW>{cnt, carry, last}, pre, fan, wt);
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       if (rd[j] != ~0u) {
         const uint32_t d = rd[j] & 255u;
         const uint32_t pos = (pre[d] & 0xFFFFu) + (rd[j] >> 8);
-        skv[pos] = make_uint2(k[j], v[j]);
+        skv[pos] = LinePair<T>::make(k[j], v[j]);
       }
     }
     // items of each digit; then the digit's output advances by the lines
     // written, its carry count becomes the new one and its pair count
     // clears (the items hold everything the write-out needs)
     for (uint32_t d = tid; d < fan; d += kPassBlock) {
-      const LinePack lp{cnt, carry, last};
+      const LinePack<LW> lp{cnt, carry, last};
       const uint32_t p = pre[d], cf = carry[d], c = cnt[d];
       const uint32_t first = p >> 16, p_low = p & 0xFFFFu;
       const uint32_t lines = lp.lines(d), tot = cf + c;
@@ -700,7 +719,7 @@ __device__ __forceinline__ void scatter_lines_range(const uint32_t* __restrict__
       const uint4 ld = line_desc[it];
       const uint32_t cbase = ld.z & 0x7FFFu;
       if (ld.w >> 31) {
-        uint2 kv = make_uint2(kEmptyKey, 0u);
+        Pair kv = LinePair<T>::pad();
         if (l < ((ld.w >> 8) & 63u)) kv = skv[l < (ld.w & 63u) ? cbase + l : ld.y + l];
         out_k[ld.x + l] = kv.x;
         out_v[ld.x + l] = kv.y;
@@ -716,7 +735,8 @@ __device__ __forceinline__ void scatter_lines_range(const uint32_t* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kPassBlock, 1) void part_scatter_lines_kernel(PartPassT<uint32_t> p) {
+template <typename T>
+__global__ __launch_bounds__(kPassBlock, 1) void part_scatter_lines_kernel(PartPassT<T> p) {
   uint32_t seg;
   uint64_t begin, end;
   if (!part_chunk(p, blockIdx.x, &seg, &begin, &end)) return;
@@ -725,7 +745,7 @@ __global__ __launch_bounds__(kPassBlock, 1) void part_scatter_lines_kernel(PartP
   const PartPlan& P = p.P;
   const uint32_t level = p.level;
   scatter_lines_range(p.in_k, p.in_v, begin, end, p.fan, p.padded != 0,
-                      [&](uint32_t k) { return part_digit(P, level, k); }, h, cur, p.out_k,
+                      [&](T k) { return part_digit(P, level, k); }, h, cur, p.out_k,
                       p.out_v);
 }
 

@@ -31,7 +31,8 @@ __global__ __launch_bounds__(kPassBlock) void part_hist64_kernel(PartPass64 p) {
   const PartPlan& P = p.P;
   const uint32_t level = p.level;
   const bool sentinel = hist_range(p.in_k, begin, end, p.fan,
-                                   [&](uint64_t k) { return part_digit(P, level, k); }, h, tot);
+                                   [&](uint64_t k) { return part_digit(P, level, k); }, h, tot,
+                                   p.padded != 0, p.lines ? line_words<uint64_t>() : 0u);
   if (level == 1 && sentinel) atomicOr(p.status, kFlagSentinel);
 }
 
@@ -44,7 +45,8 @@ __global__ __launch_bounds__(kPassBlock, kScatterBlocksPerCU) void part_scatter6
   const PartPlan& P = p.P;
   const uint32_t level = p.level;
   scatter_range(p.in_k, p.in_v, begin, end, p.fan,
-                [&](uint64_t k) { return part_digit(P, level, k); }, h, cur, p.out_k, p.out_v);
+                [&](uint64_t k) { return part_digit(P, level, k); }, h, cur, p.out_k, p.out_v,
+                p.padded != 0);
 }
 
 struct BinArgs64 {
@@ -100,7 +102,9 @@ __device__ __forceinline__ uint32_t place_bin64(const BinArgs64& a, uint32_t R, 
       fb[j] = ~0u;
       fr[j] = 0;
       const uint64_t i = r0 + j * kBinBlock + threadIdx.x;
-      if (i < len) {
+      // the empty key marks padding of a line-writing pass (a caller's
+      // reserved key has already failed the build)
+      if (i < len && k[j] != kEmpty64) {
         // lb < nb by construction of the partition
         const uint32_t lb = (uint32_t)(hash64(H, 0, k[j]) - first);
         if (lb >= nb) {

@@ -122,16 +122,26 @@ def test_wide_partitioned_build(n, lf):
     t.close()
 
 
-def test_wide_partitioned_two_passes():
+@pytest.mark.parametrize("n,padded", [(4_500_000, (True, False)), (1 << 25, (True, True))])
+def test_wide_partitioned_two_passes(n, padded):
     """4,500,000 pairs at load 0.9: 1,221 bins of 512 buckets, two radix
-    passes (the first through the slot array)."""
-    n = 4_500_000
+    passes (the first through the slot array); 2^25 pairs: 9,103 bins.  A
+    pass writes whole 128-byte lines of 16 keys (ranges padded with the
+    empty key) unless its padding would be heavy (the second pass of the
+    smaller build, with 16 K-pair chunks)."""
+    import paper_2108_07232_amd as bht
     print("wide partitioned two-pass n=%d" % n, flush=True)
     t, p, keys, vals = build_mode64(n, 0.9, 8, "partitioned")
     assert plan_levels64(p.m) == 2
     code, msg = oracle.check64(p, t.download(), keys, vals)
     assert code == 0, msg
     check(t, keys, vals, datagen.mixed_queries(n, 1 << 21, 0.5, 8, wide=True))
+    ranges = -(-n // 16384) * 256
+    for pad, on in zip(bht.bht_build_padding(t.handle), padded):
+        if on:
+            assert 0 < pad <= 15 * ranges and (n + pad) % 16 == 0
+        else:
+            assert pad == 0
     t.close()
 
 
