@@ -162,10 +162,11 @@ def measure_ceilings(bht, table, torch, stream):
 
 
 def kernel_source_sha():
-    """SHA-256 prefix of the sources that define the build and find kernels."""
+    """SHA-256 prefix of the sources that define the build and find kernels
+    and their launches (tile width, grids, partition plan)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("bht_hash.hpp", "bht_kernels.hpp", "bht_partition.hpp"):
+    for name in ("bht_hash.hpp", "bht_kernels.hpp", "bht_partition.hpp", "bht.hip"):
         h.update(open(os.path.join(ROOT, "paper_2108_07232_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -1412,7 +1413,8 @@ def run_headline(args):
     ach = kernels[dominant]["achieved_gbs"]
     traffic = None
     recorded = recorded_traffic()
-    if recorded and recorded.get("n") == n and dominant in recorded:
+    default_launch = args.tile is None and args.schedule == "default" and args.grid == 0
+    if recorded and default_launch and recorded.get("n") == n and dominant in recorded:
         traffic = recorded[dominant]
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,

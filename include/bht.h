@@ -272,7 +272,8 @@ bht_status bht_get_probe_stats(const bht_table* t, uint64_t* build_probes, uint6
 
 /* Tuning (speed only, never results).  tile_width: lanes that read one
  * bucket together (1 for bucket_size 1; 4, 8 or 16 otherwise, at most
- * bucket_size; 0 keeps the default).  find_schedule: BHT_FIND_DEFAULT,
+ * bucket_size; 0 keeps the default: 4 for BCHT and CHT1 tables of 16-slot
+ * buckets, one 16-byte load per lane for the rest).  find_schedule: BHT_FIND_DEFAULT,
  * BHT_FIND_REFILL (a lane that finishes a query takes the next one) or
  * BHT_FIND_CHUNK (a wave answers 64 consecutive queries per chunk and writes
  * their results together) or BHT_FIND_PARALLEL (BCHT and CHT1 only: all h

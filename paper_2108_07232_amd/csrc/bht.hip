@@ -258,13 +258,16 @@ bool valid_params(const bht_params& p, bht_scheme scheme, uint32_t b, std::strin
   return true;
 }
 
+// Lanes per bucket read.  A cuckoo table of 16-slot buckets takes 4 lanes
+// (32 bytes each): twice the queries or insertions of 8-lane tiles in flight
+// per wave, which the latency-bound overflow insertion (-2.5%) and the
+// queries (-0.3%) gain from; the other schemes keep one 16-byte load per lane.
 uint32_t default_tile(bht_scheme scheme, uint32_t b) {
-  (void)scheme;
   switch (b) {
     case 1: return 1;
     case 4: return 4;
     case 8: return 8;
-    case 16: return 8;
+    case 16: return (scheme == BHT_BCHT || scheme == BHT_CHT1) ? 4 : 8;
     default: return 16;
   }
 }

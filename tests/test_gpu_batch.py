@@ -83,7 +83,7 @@ def test_batch_equals_plain_calls_and_reports_failures():
     p = bad["params"]
     bad["table"].close()
     n = bad["n"]
-    bad["table"] = bht.Table(n, 16, "bcht", p.a, p.c, max_chain=0)
+    bad["table"] = bht.Table(n, 16, "bcht", p.a, p.c, tile=8, max_chain=0)
     entries = [(d["table"].handle, d["dk"], d["dv"], d["dq"], d["ov"], d["of"]) for d in tabs]
     batch = bht.bht_batch_create(entries)
     bht.bht_batch_run(batch)              # null stream: direct launches
@@ -194,7 +194,7 @@ def test_batch_build_find_one_call():
     bad = tabs[4]
     p = bad["params"]
     bad["table"].close()
-    bad["table"] = bht.Table(bad["n"], 16, "bcht", p.a, p.c, max_chain=0)
+    bad["table"] = bht.Table(bad["n"], 16, "bcht", p.a, p.c, tile=8, max_chain=0)
     entries = [(d["table"].handle, d["dk"], d["dv"], d["dq"], d["ov"], d["of"]) for d in tabs]
     rc, sts = bht.bht_batch_build_find(entries, item_size=1024)
     assert rc == bht.BHT_ERR_BUILD_FAILED and sts[4] == bht.BHT_ERR_BUILD_FAILED
