@@ -258,10 +258,12 @@ bool valid_params(const bht_params& p, bht_scheme scheme, uint32_t b, std::strin
   return true;
 }
 
-// Lanes per bucket read.  A cuckoo table of 16-slot buckets takes 4 lanes
-// (32 bytes each): twice the queries or insertions of 8-lane tiles in flight
-// per wave, which the latency-bound overflow insertion (-2.5%) and the
-// queries (-0.3%) gain from; the other schemes keep one 16-byte load per lane.
+// Lanes per bucket read.  Every lane owns one operation whatever the width;
+// the width only splits each bucket read among a tile's lanes.  A cuckoo
+// table of 16-slot buckets takes 4 lanes of 32 bytes (two 16-byte loads per
+// bucket per lane, half the bucket-index shuffles and match ballots of 8
+// lanes): measured 2.5% faster in the overflow insertion and 0.3% in the
+// queries.  The other schemes keep one 16-byte load per lane.
 uint32_t default_tile(bht_scheme scheme, uint32_t b) {
   switch (b) {
     case 1: return 1;
