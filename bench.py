@@ -162,12 +162,17 @@ def measure_ceilings(bht, table, torch, stream):
 
 
 def kernel_source_sha():
-    """SHA-256 prefix of the sources that define the build and find kernels
-    and their launches (tile width, grids, partition plan)."""
+    """SHA-256 prefix of the code (comments and blank lines removed) of the
+    sources that define the build and find kernels and their launches (tile
+    width, grids, partition plan)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("bht_hash.hpp", "bht_kernels.hpp", "bht_partition.hpp", "bht.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2108_07232_amd", "csrc", name), "rb").read())
+        text = open(os.path.join(ROOT, "paper_2108_07232_amd", "csrc", name)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()[:16]
 
 

@@ -261,9 +261,11 @@ bool valid_params(const bht_params& p, bht_scheme scheme, uint32_t b, std::strin
 // Lanes per bucket read.  Every lane owns one operation whatever the width;
 // the width only splits each bucket read among a tile's lanes.  A cuckoo
 // table of 16-slot buckets takes 4 lanes of 32 bytes (two 16-byte loads per
-// bucket per lane, half the bucket-index shuffles and match ballots of 8
-// lanes): measured 2.5% faster in the overflow insertion and 0.3% in the
-// queries.  The other schemes keep one 16-byte load per lane.
+// bucket per lane): its query and overflow kernels need 70 registers per
+// lane instead of 82 and keep 7 waves per SIMD instead of 5, measured 0.3%
+// faster in the queries and 2.5% in the overflow insertion (2 lanes: queries
+// 1.5% slower; 1 lane: 9% slower).  The other schemes keep one 16-byte load
+// per lane.
 uint32_t default_tile(bht_scheme scheme, uint32_t b) {
   switch (b) {
     case 1: return 1;

@@ -75,6 +75,22 @@ def test_recorded_traffic_requires_matching_kernel_source(tmp_path, monkeypatch)
     assert bench.recorded_traffic() is None
 
 
+def test_kernel_source_sha_ignores_comments_not_code(tmp_path, monkeypatch):
+    """The traffic record's key follows the code of the kernel and launch
+    sources: a comment edit keeps it, a code edit changes it."""
+    csrc = tmp_path / "paper_2108_07232_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    names = ("bht_hash.hpp", "bht_kernels.hpp", "bht_partition.hpp", "bht.hip")
+    for nm in names:
+        (csrc / nm).write_text("int f() { return 4; }  // lanes\n/* block\n comment */\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    base = bench.kernel_source_sha()
+    (csrc / "bht.hip").write_text("// new words\n\nint f() { return 4; }  // other words\n")
+    assert bench.kernel_source_sha() == base
+    (csrc / "bht.hip").write_text("int f() { return 8; }\n")
+    assert bench.kernel_source_sha() != base
+
+
 def test_committed_traffic_line_parses():
     """The committed summary carries one machine-readable line with the
     figures the benchmark reports."""
