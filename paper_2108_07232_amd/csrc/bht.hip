@@ -5,10 +5,12 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
+#include <utility>
 #include <vector>
 
 #include "bht.h"
@@ -132,6 +134,23 @@ constexpr uint64_t kLbPairsPerLane = BHT_LB_PAIRS_PER_LANE;
 #define BHT_ICEBERG_OVF_SPREAD 1
 #endif
 constexpr uint64_t kIcebergOverflowSpread = BHT_ICEBERG_OVF_SPREAD;
+
+// Blocks of `block` threads of `kernel` the current device keeps resident.
+int resident_blocks(const void* kernel, int block) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> known;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = known.find({kernel, dev});
+  if (it != known.end()) return it->second;
+  int cus = 0, per_cu = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
+  const int cap = std::max(1, cus) * std::max(1, per_cu);
+  known.emplace(std::make_pair(kernel, dev), cap);
+  return cap;
+}
 
 // Blocks to launch: enough to give every lane an item, capped at what the
 // device keeps resident at once (the kernels loop over their share).
@@ -469,6 +488,14 @@ uint32_t log2_exact(uint64_t x) {
   return r;
 }
 
+// Second-pass chunks the workspace provides for: the count of pieces of at
+// most one chunk per first-pass range (`ceil_chunks`, a bound), plus a
+// quarter more (at most 512) for the round-balanced cuts part_scan1_kernel
+// may choose; each chunk adds up to kLinePadPerChunk2 words of padding room.
+uint64_t second_pass_chunk_cap(uint64_t ceil_chunks) {
+  return ceil_chunks + std::min<uint64_t>(ceil_chunks / 4, 512);
+}
+
 // Bins, passes, digit counts and chunk size for n pairs; false if the table
 // has more bins than two passes can address.  Bins are as large as LDS
 // allows, halved (down to 32 buckets) while a single pass still covers them,
@@ -517,10 +544,14 @@ bool part_plan(const bht_table* t, uint64_t n, PartPlan* P) {
                   mid < (1ull << 32);
       const uint64_t in = P->lines1 ? in2 : n;
       const uint64_t chunks2 = in / P->chunk + P->fan1;
+      P->chunks2_cap = (uint32_t)second_pass_chunk_cap(chunks2);
       P->lines2 = light(chunks2, kFan2) &&
-                  in + chunks2 * kLinePadPerChunk2 + kLineWords * (P->fan1 + 1) < (1ull << 32);
+                  in + P->chunks2_cap * kLinePadPerChunk2 + kLineWords * (P->fan1 + 1) <
+                      (1ull << 32);
     }
   }
+  if (P->levels == 2 && !P->chunks2_cap)
+    P->chunks2_cap = (uint32_t)second_pass_chunk_cap(n / P->chunk + P->fan1);
   return true;
 }
 
@@ -545,7 +576,7 @@ PartLayout part_layout(const PartPlan& P, uint64_t n, uint32_t word_bytes = 4) {
   // first-pass output words, padding included
   const uint64_t in2 =
       n + (P.lines1 ? line_pad_bound(L.chunks1, P.fan1, n, 128 / word_bytes) : 0);
-  L.chunks2 = P.levels == 2 ? in2 / P.chunk + P.fan1 : 0;
+  L.chunks2 = P.levels == 2 ? P.chunks2_cap : 0;
   L.mid_words = P.levels == 2 ? (P.lines1 ? round_to_line(in2) : n) : 0;
   L.out_words = in2 + (P.lines2 ? L.chunks2 * kLinePadPerChunk2 + kLineWords * (P.fan1 + 1) : 0);
   L.hist1 = take(L.chunks1 * P.fan1 * 4);
@@ -652,6 +683,13 @@ void launch_radix(const PartPlan& P, const PartMeta& M, const PartLayout& L, con
     scatter = part_scatter64_kernel;
     scatter_lines = part_scatter_lines_kernel<uint64_t>;
   }
+  // The second pass's chunks are cut for its scatter's rounds of resident
+  // blocks.
+  PartPlan Q = P;
+  Q.resident2 = P.levels == 2
+                    ? (uint32_t)resident_blocks((const void*)(P.lines2 ? scatter_lines : scatter),
+                                                kPassBlock)
+                    : 0u;
   part_clear_kernel<<<64, kPartBlock, 0, st>>>(M, P.fan1, P.levels, status);
   PartPassT<T> p1;
   p1.in_k = keys;
@@ -664,10 +702,10 @@ void launch_radix(const PartPlan& P, const PartMeta& M, const PartLayout& L, con
   p1.lines = P.lines1;
   p1.padded = 0;
   p1.status = status;
-  p1.P = P;
+  p1.P = Q;
   p1.M = M;
   hist<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
-  part_scan1_kernel<<<1, kPartBlock, 0, st>>>(P, M, status);
+  part_scan1_kernel<<<1, kPartBlock, 0, st>>>(Q, M, status);
   (P.lines1 ? scatter_lines : scatter)<<<(unsigned)L.chunks1, kPassBlock, 0, st>>>(p1);
   if (P.levels == 2) {
     PartPassT<T> p2 = p1;
@@ -680,7 +718,7 @@ void launch_radix(const PartPlan& P, const PartMeta& M, const PartLayout& L, con
     p2.lines = P.lines2;
     p2.padded = P.lines1;
     hist<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
-    part_scan2_kernel<<<P.fan1, kPartBlock, 0, st>>>(P, M, status);
+    part_scan2_kernel<<<P.fan1, kPartBlock, 0, st>>>(Q, M, status);
     (P.lines2 ? scatter_lines : scatter)<<<(unsigned)L.chunks2, kPassBlock, 0, st>>>(p2);
   }
 }

@@ -102,6 +102,8 @@ struct PartPlan {
   uint32_t chunk;       // pairs per partition block (a multiple of the sub-tile)
   uint32_t lines1;      // the first pass writes whole lines (ranges padded with the empty key)
   uint32_t lines2;      // the same for the second pass
+  uint32_t chunks2_cap; // second-pass chunks the workspace holds
+  uint32_t resident2;   // second-pass scatter blocks resident at once (0: unknown)
 };
 
 // Words of T per 128-byte line, and the words of a (chunk, digit) range of
@@ -177,14 +179,20 @@ __device__ __forceinline__ bool part_chunk(const PartPassT<T>& p, uint32_t blk, 
     *end = b + C < p.n ? b + C : p.n;
     return true;
   }
+  (void)C;
+  // A second-pass range of len words is cut into k chunks of equal length
+  // (cuts on whole lines), k chosen by part_scan1_kernel.
   const uint32_t* cf = p.M.chunk_first;
   if (blk >= cf[p.P.fan1]) return false;
   const uint32_t lo = p.M.chunk_seg[blk];  // cf[lo] <= blk < cf[lo + 1]
-  const uint64_t s0 = p.M.seg_start[lo], s1 = s0 + p.M.seg_len[lo];
-  const uint64_t b = s0 + (uint64_t)(blk - cf[lo]) * C;
+  const uint64_t s0 = p.M.seg_start[lo], len = p.M.seg_len[lo];
+  const uint32_t j = blk - cf[lo], k = cf[lo + 1] - cf[lo];
+  auto cut = [&](uint32_t i) -> uint64_t {
+    return i >= k ? len : ((uint64_t)i * len / k) & ~(uint64_t)(kLineWords - 1);
+  };
   *seg = lo;
-  *begin = b;
-  *end = b + C < s1 ? b + C : s1;
+  *begin = s0 + cut(j);
+  *end = s0 + cut(j + 1);
   return true;
 }
 
@@ -266,8 +274,8 @@ __device__ __forceinline__ bool hist_range(const T* __restrict__ in_k, uint64_t 
   __syncthreads();
   bool sentinel = false;
   constexpr int U = 8;
-  // 32-bit offsets from the range's start (a range is one chunk, at most
-  // kPartChunkMax pairs), so the address arithmetic stays in single registers
+  // 32-bit offsets from the range's start (a range is one chunk, under 2^32
+  // pairs), so the address arithmetic stays in single registers
   const T* __restrict__ kb = in_k + begin;
   const uint32_t len = (uint32_t)(end - begin);
   for (uint32_t base = 0; base < len; base += U * kPassBlock) {
@@ -325,6 +333,100 @@ __global__ __launch_bounds__(kPassBlock) void part_hist_kernel(PartPassT<T> p) {
 constexpr int kStatusPass1Words = 4;
 constexpr int kStatusPass2Words = 6;
 
+// Chunks of the second pass: how many equal pieces each first-pass range
+// (len[d] words of `words` in all) is cut into.  The pass's blocks run in
+// rounds of `resident2` (one block per CU for the scatter), so the pass
+// takes about ceil(chunks / resident2) times its longest chunk.  Candidate 0
+// cuts each range into pieces of at most P.chunk words; candidates 1-4 aim
+// at K = r * resident2 chunks in all (r around candidate 0's rounds) and give
+// range d floor(len[d] * K / words) of them, at least 1 and at most one per
+// 64 words, so their sum stays within K wherever the ranges are not tiny.
+// The cheapest estimate wins (ties: fewer chunks); candidates over the
+// workspace bound are skipped.  Every thread of the block calls it.
+__device__ __forceinline__ void split_ranges(const PartPlan& P,
+                                             const unsigned long long* __restrict__ len,
+                                             unsigned long long words,
+                                             unsigned long long* __restrict__ chunks) {
+  constexpr int kCand = 5;
+  __shared__ unsigned int sum[kCand], longest[kCand];
+  __shared__ unsigned long long target[kCand];
+  __shared__ int pick;
+  const uint32_t R = P.resident2;
+  // range lengths are below 2^32 words (positions are 32-bit)
+  auto pieces = [&](int c, uint32_t l) -> uint32_t {
+    if (l == 0) return 0;
+    if (c == 0) return (uint32_t)(((uint64_t)l + P.chunk - 1) / P.chunk);
+    uint32_t k = (uint32_t)((double)l * (double)target[c] / (double)words);
+    const uint32_t most = l / 64 > 1 ? l / 64 : 1;
+    k = k < 1 ? 1 : k;
+    return k < most ? k : most;
+  };
+  // per-thread partial sums and maxima, reduced per wave, one LDS atomic
+  // per wave (same-address atomics from every lane would serialize)
+  auto wave_max = [](uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+  };
+  const bool lead = (threadIdx.x & 63) == 0;
+  if (threadIdx.x < kCand) {
+    sum[threadIdx.x] = 0;
+    longest[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  {
+    uint32_t part = 0;
+    for (uint32_t d = threadIdx.x; d < P.fan1; d += kPartBlock)
+      part += (uint32_t)pieces(0, len[d]);
+    part = wave_sum(part);
+    if (lead) atomicAdd(&sum[0], part);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long rounds0 = R ? ((long long)sum[0] + R - 1) / R : 0;
+    for (int c = 1; c < kCand; ++c) {
+      const long long r = rounds0 + c - 2;
+      target[c] = R && words ? (unsigned long long)(r > 1 ? r : 1) * R : 0;
+    }
+  }
+  __syncthreads();
+  for (int c = 0; c < kCand; ++c) {
+    uint32_t part = 0, most = 0;
+    if (c == 0 || target[c] != 0) {
+      for (uint32_t d = threadIdx.x; d < P.fan1; d += kPartBlock) {
+        const uint32_t l = (uint32_t)len[d];
+        const uint32_t k = (uint32_t)pieces(c, l);
+        part += k;
+        if (k) most = max(most, (uint32_t)(((uint64_t)l + k - 1) / k));
+      }
+    }
+    part = wave_sum(part);
+    most = wave_max(most);
+    if (lead) {
+      if (c > 0) atomicAdd(&sum[c], part);
+      atomicMax(&longest[c], most);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int best = 0;
+    unsigned long long best_cost = ~0ull;
+    for (int c = 0; c < kCand; ++c) {
+      if (c > 0 && (target[c] == 0 || sum[c] > P.chunks2_cap)) continue;
+      const unsigned long long rounds = R ? (sum[c] + R - 1) / R : 1;
+      const unsigned long long cost = rounds * longest[c];
+      if (cost < best_cost || (cost == best_cost && sum[c] < sum[best])) {
+        best = c;
+        best_cost = cost;
+      }
+    }
+    pick = best;
+  }
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < P.fan1; d += kPartBlock)
+    chunks[d] = pieces(pick, (uint32_t)len[d]);
+  __syncthreads();
+}
+
 // First-pass totals -> output ranges.  One block.  With one pass the digits
 // are the bins; with two, the ranges of the second pass and its chunk counts.
 __global__ __launch_bounds__(kPartBlock) void part_scan1_kernel(PartPlan P, PartMeta M,
@@ -345,11 +447,10 @@ __global__ __launch_bounds__(kPartBlock) void part_scan1_kernel(PartPlan P, Part
     } else {
       M.seg_start[d] = base[d];
       M.seg_len[d] = c;
-      chunks[d] = (c + P.chunk - 1) / P.chunk;
     }
   }
   if (P.levels == 1) return;          // uniform
-  __syncthreads();
+  split_ranges(P, M.total1, words, chunks);
   const unsigned long long total =
       block_exclusive_scan<kPartBlock, unsigned long long>(chunks, base, P.fan1, wt);
   for (uint32_t d = threadIdx.x; d < P.fan1; d += kPartBlock) {
@@ -426,9 +527,8 @@ __device__ __forceinline__ void scatter_range(const T* __restrict__ in_k,
   // Loads are branch-free (offsets past the end re-read the last pair, and
   // those copies are never ranked), so the compiler can leave the next
   // sub-tile's loads in flight while the current one is ranked.  Offsets
-  // are 32-bit, from the range's start (a range is one chunk, at most
-  // kPartChunkMax pairs), so the address arithmetic stays in single
-  // registers.
+  // are 32-bit, from the range's start (a range is one chunk, under 2^32
+  // pairs), so the address arithmetic stays in single registers.
   const T* __restrict__ kb = in_k + begin;
   const T* __restrict__ vb = in_v + begin;
   const uint32_t len = (uint32_t)(end - begin);
