@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=None)
     ap.add_argument("--schedule", default="default", choices=["default", "refill", "chunk", "parallel"])
     ap.add_argument("--grid", type=int, default=0, help="blocks per launch (0 = resident)")
+    ap.add_argument("--unroll", type=int, default=0, choices=[0, 1, 2],
+                    help="queries per lane per chunk (0 = the library default)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-log2n", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1270,7 +1272,8 @@ def run_headline(args):
     seed_try = args.seed
     a, c = datagen.hash_constants(seed_try, 3)
     table = bht.Table(cap, args.bucket, "bcht", a, c, rng_seed=datagen.rng_seed(seed_try),
-                      tile=args.tile, find_schedule=args.schedule, grid_blocks=args.grid)
+                      tile=args.tile, find_schedule=args.schedule, grid_blocks=args.grid,
+                      query_unroll=args.unroll)
     bht.bht_enable_timing(table.handle, True)
     m, b, _, table_bytes = table.info
     stream = torch.cuda.current_stream()
@@ -1418,7 +1421,8 @@ def run_headline(args):
     ach = kernels[dominant]["achieved_gbs"]
     traffic = None
     recorded = recorded_traffic()
-    default_launch = args.tile is None and args.schedule == "default" and args.grid == 0
+    default_launch = (args.tile is None and args.schedule == "default" and args.grid == 0
+                      and args.unroll == 0)
     if recorded and default_launch and recorded.get("n") == n and dominant in recorded:
         traffic = recorded[dominant]
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": ach, "peak": HBM_PEAK_GBS,

@@ -308,7 +308,8 @@ bht_status bht_get_probe_stats(const bht_table* t, uint64_t* build_probes, uint6
  * such a negative query costs one probe instead of three.  0 (default)
  * probes every candidate, as Section V-D describes.  query_unroll (chunk
  * schedule, single-table and batched queries): queries per lane per chunk,
- * 1 (0 = 1) or 2; the autotuner of the batched mode chooses it. */
+ * 1 or 2 (0 = the default: 2 for BCHT and CHT1 tables of 16-slot buckets,
+ * else 1); the autotuner of the batched mode chooses it. */
 typedef enum {
   BHT_FIND_DEFAULT = 0,
   BHT_FIND_REFILL = 1,

@@ -108,8 +108,8 @@ def test_batch_equals_plain_calls_and_reports_failures():
 
 def test_batch_rejects_mixed_query_unroll():
     import paper_2108_07232_amd as bht
-    tabs = make_tables(4, 8, 10, 21)
-    bht.bht_set_tuning(tabs[2]["table"].handle, 8, 0, 0, 0, False, 2)
+    tabs = make_tables(4, 8, 10, 21, unroll=2)
+    bht.bht_set_tuning(tabs[2]["table"].handle, 8, 0, 0, 0, False, 1)
     entries = [(d["table"].handle, d["dk"], d["dv"], d["dq"], d["ov"], d["of"]) for d in tabs]
     with pytest.raises(bht.BhtError) as e:
         bht.bht_batch_create(entries)
